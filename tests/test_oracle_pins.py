@@ -1,0 +1,573 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a physics
+closed form (work-energy, uniform-acceleration kinematics, the equivalent
+circuit), an exact property of multilinear interpolation, brute-force
+enumeration on tiny problems written here independently, invariants of the
+recursion (signal constraint, lower bound, decoupling, occupancy), finite
+differences of fresh solves, and the workload arithmetic the paper states.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_01284_amd import instances as ins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+JINF = ins.J_INF
+
+
+def grid(lo, hi, n):
+    return np.array([lo + i * ((hi - lo) / (n - 1)) for i in range(n)]) if n > 1 else np.array([lo])
+
+
+def physics_inst(M=1600.0, CdA=0.7, Crr=0.01, grade=0.0):
+    inst = ins.tiny(seed=3, N=2, flat=True, light=False)
+    inst["grade"] = np.full(inst["N"], grade)
+    inst["theta"] = [M, CdA, Crr, 0.5, 5000.0]
+    return inst
+
+
+# ---------------------------------------------------------------- physics --
+
+def test_coast_down_rolling_resistance():
+    """Eq. 5a, engine and motor off, no drag, flat: a uniform deceleration
+    mu*g, so v1^2 = v^2 - 2 mu g dd (kinematics)."""
+    inst = physics_inst(CdA=0.0)
+    g = inst["konst"][0]
+    for v in (3.0, 7.5, 12.0, 19.0):
+        st, o = oracle.transition(inst, 0, v, 0.5, 0, 1)   # T_eng = 0, T_mot = 0
+        assert st == 0
+        assert o["v1"] == pytest.approx(math.sqrt(v * v - 2 * 0.01 * g * 10.0), rel=1e-13)
+        assert o["acc"] == pytest.approx(-0.01 * g, rel=1e-13)
+        assert o["mf"] == 0.0
+
+
+def test_downhill_energy_conservation():
+    """Frictionless coast on a slope: kinetic energy gained equals potential
+    energy lost over the height drop dd*sin(alpha), alpha = atan(grade)."""
+    G = -0.03
+    inst = physics_inst(CdA=0.0, Crr=0.0, grade=G)
+    g = inst["konst"][0]
+    drop = 10.0 * math.sin(math.atan(-G))
+    for v in (2.0, 10.0, 18.0):
+        st, o = oracle.transition(inst, 0, v, 0.5, 0, 1)
+        assert st == 0
+        assert 0.5 * o["v1"] ** 2 - 0.5 * v * v == pytest.approx(g * drop, rel=1e-12)
+
+
+def test_aero_drag_work():
+    """Drag alone: M (v1^2 - v^2)/2 = -(rho CdA v^2 / 2) dd (textbook drag
+    force held at the step's initial speed)."""
+    inst = physics_inst(CdA=0.7, Crr=0.0)
+    rho = inst["konst"][1]
+    for v in (5.0, 15.0):
+        st, o = oracle.transition(inst, 0, v, 0.5, 0, 1)
+        assert 0.5 * 1600.0 * (o["v1"] ** 2 - v * v) == pytest.approx(-0.5 * rho * 0.7 * v * v * 10.0, rel=1e-12)
+
+
+def test_traction_work():
+    """Work-energy with only the powertrain force: eta_dl (T_eng + T_mot)
+    i_g / r_w acting over dd."""
+    inst = physics_inst(CdA=0.0, Crr=0.0)
+    K = inst["konst"]
+    st, o = oracle.transition(inst, 0, 8.0, 0.5, 2, 2)   # 150 Nm + 100 Nm
+    F = K[4] * 250.0 * K[3] / K[2]
+    assert 0.5 * 1600.0 * (o["v1"] ** 2 - 64.0) == pytest.approx(F * 10.0, rel=1e-12)
+
+
+def test_travel_time_uniform_acceleration():
+    """Eq. 2: dt = dd / mean speed is the time to cover dd under the uniform
+    acceleration that takes v to v1 (positive root of v t + a t^2/2 = dd)."""
+    inst = ins.tiny(seed=5, N=3, light=False)
+    rng = np.random.default_rng(0)
+    n = 0
+    for _ in range(60):
+        v = rng.uniform(0.5, 19.0)
+        a, b = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        st, o = oracle.transition(inst, 1, v, 0.5, a, b)
+        if st & 4:
+            continue
+        acc = (o["v1"] ** 2 - v * v) / 20.0
+        if abs(acc) < 1e-12:
+            t = 10.0 / v
+        else:
+            t = (-v + math.sqrt(max(v * v + 2 * acc * 10.0, 0.0))) / acc
+        assert o["dt"] == pytest.approx(t, rel=1e-9)
+        n += 1
+    assert n > 30
+
+
+def test_battery_equivalent_circuit():
+    """Eq. 5b battery: the current solves P_bat = Voc I - R I^2 on the branch
+    |I| <= Voc/(2R); motoring draws P_mech/eta_m, generating returns
+    P_mech*eta_m; demand above Voc^2/(4R) is infeasible."""
+    inst = ins.tiny(seed=5, N=3, light=False, n_m=5)
+    K = inst["konst"]
+    for v in (3.0, 8.0, 15.0):
+        for b in range(5):
+            for xi in (0.35, 0.55, 0.75):
+                st, o = oracle.transition(inst, 0, v, xi, 1, b)
+                Tm = grid(*inst["tm_grid"])[b]
+                Pm = Tm * v * K[3] / K[2]
+                Voc = K[7] + K[8] * xi
+                if Pm >= 0:
+                    assert o["P_bat"] * K[5] == pytest.approx(Pm, rel=1e-13, abs=1e-9)
+                else:
+                    assert o["P_bat"] == pytest.approx(Pm * K[5], rel=1e-13)
+                if o["P_bat"] > Voc * Voc / (4 * K[9]):
+                    assert st & 8
+                    continue
+                I = o["I_bat"]
+                assert Voc * I - K[9] * I * I == pytest.approx(o["P_bat"], rel=1e-10, abs=1e-9)
+                assert abs(I) <= Voc / (2 * K[9])
+
+
+def test_stage_cost_eq1():
+    """Eq. 1: (gamma mf + (1 - gamma)) dt, scaled by 1/gamma with
+    w_t = (1 - gamma)/gamma; engine off burns no fuel."""
+    inst = ins.tiny(seed=5, N=3, light=False)
+    wt = inst["theta"][3]
+    gamma = 1.0 / (1.0 + wt)
+    for a in range(3):
+        st, o = oracle.transition(inst, 0, 9.0, 0.5, a, 1)
+        assert gamma * o["cost"] == pytest.approx(gamma * o["mf"] * o["dt"] + (1 - gamma) * o["dt"], rel=1e-13)
+        if a == 0:
+            assert o["mf"] == 0.0 and o["cost"] == pytest.approx(wt * o["dt"], rel=1e-15)
+
+
+# ----------------------------------------------------------- interpolation --
+
+def test_interp_reproduces_multilinear():
+    """Trilinear interpolation is exact on functions multilinear in the three
+    index coordinates, at interior points, on nodes and on the upper faces."""
+    inst = ins.tiny(seed=2, n_v=5, n_s=4, n_t=6)
+    rng = np.random.default_rng(1)
+    c = rng.normal(size=8)
+    f = lambda x, y, z: (c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * y * z
+                         + c[6] * x * z + c[7] * x * y * z)
+    i, j, m = np.meshgrid(np.arange(5), np.arange(4), np.arange(6), indexing="ij")
+    J = f(i, j, m)
+    pts = [tuple(rng.uniform(0, [4, 3, 5])) for _ in range(200)]
+    pts += [(4.0, 3.0, 5.0), (0.0, 0.0, 0.0), (2.0, 1.0, 3.0), (4.0, 1.5, 2.25), (0.5, 3.0, 5.0)]
+    for p in pts:
+        assert oracle.interp(inst, J, *p) == pytest.approx(f(*p), rel=1e-12, abs=1e-12)
+
+
+# ------------------------------------------------------------- brute force --
+
+def _terminal_linear(inst, alpha, beta, gam):
+    v = grid(*inst["v_grid"])
+    s = grid(*inst["soc_grid"])
+    t = grid(*inst["t_grid"])
+    return alpha * v[:, None, None] + beta * s[None, :, None] + gam * t[None, None, :]
+
+
+def _succ_linear_value(inst, k, v, xi, t, a, b, coef):
+    """Exact continuous successor and the linear terminal value there; None if
+    the step or the successor leaves the admissible set."""
+    st, o = oracle.transition(inst, k, v, xi, a, b)
+    if st:
+        return None
+    v1 = o["v1"]
+    xi1 = xi - o["dt"] * o["I_bat"] / inst["konst"][6]
+    t1 = t + o["dt"]
+    (vl, vh, _), (sl, sh, _), (_, tf, _) = inst["v_grid"], inst["soc_grid"], inst["t_grid"]
+    eps = 1e-12
+    if not (vl - eps <= v1 <= vh + eps and sl - eps <= xi1 <= sh + eps and t1 <= tf + eps):
+        return None
+    return o["cost"] + coef[0] * v1 + coef[1] * xi1 + coef[2] * t1
+
+
+def test_single_stage_bruteforce_linear_terminal():
+    """N = 1 with a terminal cost linear in (v, SoC, t): interpolation is then
+    exact, so each node's J_0 must equal the brute-force minimum over all
+    controls of cost + terminal at the exact successor, and the root V_0 the
+    same at the off-grid x0."""
+    inst = ins.tiny(seed=21, N=1, n_v=6, n_s=5, n_t=7, n_e=4, n_m=5, light=False, t_f=12.0)
+    inst["theta"][4] = 0.0
+    coef = (0.7, -30.0, 0.2)
+    inst["terminal_V"] = _terminal_linear(inst, *coef)
+    r = oracle.solve(inst)
+    v = grid(*inst["v_grid"])
+    s = grid(*inst["soc_grid"])
+    t = grid(*inst["t_grid"])
+    nu = 20
+    checked = 0
+    for i in range(6):
+        for j in range(5):
+            for m in range(7):
+                vals = [_succ_linear_value(inst, 0, v[i], s[j], t[m], u // 5, u % 5, coef) for u in range(nu)]
+                vals = [JINF if x is None or x >= JINF else x for x in vals]
+                best = min(vals)
+                assert r["J"][0, i, j, m] == pytest.approx(best, rel=1e-11, abs=1e-9)
+                if best < JINF:
+                    srt = sorted(vals)
+                    if srt[1] - srt[0] > 1e-8:
+                        assert r["pi"][0, i, j, m] == int(np.argmin(vals))
+                    checked += 1
+    assert checked > 50
+    vals = [_succ_linear_value(inst, 0, inst["v0"], inst["soc0"], 0.0, u // 5, u % 5, coef) for u in range(nu)]
+    vals = [JINF if x is None else x for x in vals]
+    assert r["V0"] == pytest.approx(min(vals), rel=1e-11)
+    assert r["u0"] == int(np.argmin(vals))
+
+
+def _tri_weights(r, n):
+    """Independent corner list of multilinear interpolation: [(node tuple, weight)]."""
+    per = []
+    for d in range(3):
+        c = min(int(math.floor(r[d])), n[d] - 2)
+        f = r[d] - c
+        per.append([(c, 1 - f), (c + 1, f)])
+    out = []
+    for (a, wa), (b, wb), (e, we) in itertools.product(*per):
+        w = wa * wb * we
+        if w > 0:
+            out.append(((a, b, e), w))
+    return out
+
+
+def _red(inst, L, t_rel):
+    k, C, R, O = inst["lights"][L]
+    ph = math.fmod(inst["t0_abs"] + t_rel - O, C)
+    if ph < 0:
+        ph += C
+    return ph < R, ph
+
+
+def test_markov_policy_bruteforce():
+    """Interpolated DP = minimum expected cost over all deterministic Markov
+    policies of the chain that jumps to the bracketing nodes with the
+    interpolation weights (each node may also pay J_inf).  Tiny problem:
+    N = 2, 2x2x2 nodes, 3 controls, a signal at stage 1; every policy is
+    enumerated."""
+    inst = ins.tiny(seed=8, N=2, n_v=2, n_s=2, n_t=2, n_e=1, n_m=3, light=False, t_f=12.0)
+    inst["te_grid"] = (40.0, 40.0, 1)
+    inst["v_grid"] = (0.0, 16.0, 2)
+    inst["soc_grid"] = (0.3, 0.8, 2)
+    inst["v0"], inst["soc0"] = 9.0, 0.52
+    inst["konst"][12] = 0.5
+    inst["t0_abs"] = 0.0
+    inst["lights"] = [(1, 20.0, 8.0, 0.0)]    # red on [0, 8) + 20 n
+    r = oracle.solve(inst)
+    nv, ns, nt = 2, 2, 2
+    n = (nv, ns, nt)
+    v = grid(*inst["v_grid"])
+    s = grid(*inst["soc_grid"])
+    t = grid(*inst["t_grid"])
+    hv, hs, ht = v[1] - v[0], s[1] - s[0], t[1] - t[0]
+    wsoc, xref, wt = inst["theta"][4], inst["konst"][12], inst["theta"][3]
+    J2 = np.array([[[min(JINF, wsoc * (s[j] - xref) ** 2) for m in range(nt)] for j in range(ns)] for i in range(nv)])
+
+    def step(k, vv, xi, tt, u, Jn):
+        st, o = oracle.transition(inst, k, vv, xi, 0, u)
+        if st:
+            return None
+        rr = ((o["v1"] - v[0]) / hv, (xi - o["dt"] * o["I_bat"] / inst["konst"][6] - s[0]) / hs, (tt + o["dt"]) / ht)
+        if not (0 <= rr[0] <= nv - 1 and 0 <= rr[1] <= ns - 1 and 0 <= rr[2] <= nt - 1):
+            return None
+        return o["cost"], _tri_weights(rr, n)
+
+    nodes = list(itertools.product(range(nv), range(ns), range(nt)))
+    # per stage-1 node: the list of admissible actions as (cost, expected J2), J_inf always allowed
+    acts = []
+    for (i, j, m) in nodes:
+        red, ph = _red(inst, 0, t[m])
+        opts = [JINF]
+        if red:
+            if v[i] == 0.0:
+                tau = 8.0 - ph
+                rt = (t[m] + tau) / ht
+                if rt <= nt - 1:
+                    opts.append(wt * tau + sum(w * J2[i, j, e] for (_, _, e), w in
+                                               [((0, 0, c), w) for (c, w) in
+                                                [(min(int(rt), nt - 2), 1 - (rt - min(int(rt), nt - 2))),
+                                                 (min(int(rt), nt - 2) + 1, rt - min(int(rt), nt - 2))] if w > 0]))
+        else:
+            for u in range(3):
+                res = step(1, v[i], s[j], t[m], u, J2)
+                if res is not None:
+                    c, ws = res
+                    opts.append(c + sum(w * J2[a, b, e] for (a, b, e), w in ws))
+        acts.append(opts)
+    best = JINF
+    for u0 in range(3):
+        res = step(0, inst["v0"], inst["soc0"], 0.0, u0, None)
+        if res is None:
+            continue
+        c0, w0 = res
+        # enumerate every policy over the stage-1 nodes that the root reaches
+        reach = [(nodes.index(nd), w) for nd, w in w0]
+        for choice in itertools.product(*[range(len(acts[q])) for q, _ in reach]):
+            val = c0 + sum(w * acts[q][ch] for (q, w), ch in zip(reach, choice))
+            best = min(best, val)
+    best = min(best, JINF)
+    assert r["V0"] == pytest.approx(best, rel=1e-12)
+    # each node's J_1 is its own best action
+    for q, (i, j, m) in enumerate(nodes):
+        assert r["J"][1, i, j, m] == pytest.approx(min(acts[q]), rel=1e-12)
+
+
+def _openloop_bruteforce(inst):
+    """Minimum over all control sequences of the exact continuous cost, with
+    exact signal and speed checks (no grid)."""
+    N = inst["N"]
+    ne, nm = inst["te_grid"][2], inst["tm_grid"][2]
+    best = math.inf
+    wsoc, xref = inst["theta"][4], inst["konst"][12]
+    (sl, sh, _), (_, tf, _) = inst["soc_grid"], inst["t_grid"]
+    for seq in itertools.product(range(ne * nm), repeat=N):
+        v, xi, t, J = inst["v0"], inst["soc0"], 0.0, 0.0
+        ok = True
+        for k, u in enumerate(seq):
+            st, o = oracle.transition(inst, k, v, xi, u // nm, u % nm)
+            if st:
+                ok = False
+                break
+            J += o["cost"]
+            xi -= o["dt"] * o["I_bat"] / inst["konst"][6]
+            v, t = o["v1"], t + o["dt"]
+            if not (sl <= xi <= sh and t <= tf and v <= inst["v_grid"][1]):
+                ok = False
+                break
+        if ok:
+            best = min(best, J + wsoc * (xi - xref) ** 2)
+    return best
+
+
+def test_openloop_bruteforce_refinement():
+    """The grid DP approximates the continuous problem of Eq. 6: its gap to
+    the open-loop brute force over all control sequences shrinks as the state
+    grid is refined (x2 per dimension, three times)."""
+    base = ins.tiny(seed=31, N=3, n_v=5, n_s=5, n_t=5, n_e=3, n_m=3, light=False, t_f=40.0)
+    base["v0"], base["soc0"], base["konst"][12] = 10.0, 0.55, 0.55
+    bf = _openloop_bruteforce(base)
+    errs = []
+    for r in range(4):
+        inst = dict(base)
+        f = 2 ** r
+        inst["v_grid"] = (0.0, 20.0, 4 * f + 1)
+        inst["soc_grid"] = (0.3, 0.8, 4 * f + 1)
+        inst["t_grid"] = (0.0, 40.0, 4 * f + 1)
+        errs.append(abs(oracle.solve(inst)["V0"] - bf))
+    assert bf < JINF
+    assert errs[-1] < errs[0]
+    assert errs[-1] < 0.25 * errs[0]
+    assert all(errs[q + 1] <= errs[q] * 1.05 for q in range(3)), errs
+
+
+# ---------------------------------------------------------------- invariants --
+
+def test_red_phase_invariant_and_wait():
+    """Eq. 7c/8: at the signal stage every moving node in a red phase is
+    infeasible; a node at zero speed waits for the green (Eq. 5c) and its value
+    is w_t tau plus the next stage interpolated in t at t_m + tau."""
+    inst = ins.plain()
+    r = oracle.solve(inst)
+    k, C, R, O = inst["lights"][0]
+    t = grid(*inst["t_grid"])
+    ht = t[1] - t[0]
+    nt = len(t)
+    wt = inst["theta"][3]
+    n_red = 0
+    for m in range(nt):
+        red, ph = _red(inst, 0, t[m])
+        if not red:
+            continue
+        n_red += 1
+        assert np.all(r["J"][k, 1:, :, m] == JINF)
+        assert np.all(r["pi"][k, 1:, :, m] == -1)
+        tau = R - ph
+        rt = m + tau / ht
+        for j in range(inst["soc_grid"][2]):
+            if rt > nt - 1:
+                assert r["J"][k, 0, j, m] == JINF
+                continue
+            c = min(int(math.floor(rt)), nt - 2)
+            f = rt - c
+            want = wt * tau + (1 - f) * r["J"][k + 1, 0, j, c] + f * r["J"][k + 1, 0, j, c + 1]
+            assert r["J"][k, 0, j, m] == pytest.approx(min(want, JINF), rel=1e-13)
+            if want < JINF:
+                assert r["pi"][k, 0, j, m] == -2
+    assert n_red > 5
+    off = dict(inst)
+    off["flags"] = 0
+    r2 = oracle.solve(off)
+    for m in range(nt):
+        if _red(inst, 0, t[m])[0]:
+            assert np.all(r2["J"][k, :, :, m] == JINF)
+
+
+def test_lower_bound_time_cost():
+    """Every stage costs at least w_t * dd / v_hi (mean speed <= v_hi), so a
+    finite J_k is at least w_t (N - k - lights ahead) dd / v_hi."""
+    inst = ins.plain()
+    r = oracle.solve(inst)
+    N, wt, vh = inst["N"], inst["theta"][3], inst["v_grid"][1]
+    for k in range(N + 1):
+        ahead = sum(1 for L in inst["lights"] if L[0] >= k)
+        Jk = r["J"][k]
+        fin = Jk[Jk < JINF]
+        assert fin.size > 0
+        assert fin.min() >= wt * (N - k - ahead) * 10.0 / vh - 1e-9
+
+
+def test_decoupling_special_cases():
+    """(a) no motor torque and no SoC penalty: the SoC never moves and J does
+    not depend on it; (b) no signal, generous t_f: J does not depend on t at
+    early times (time enters the cost only through dt)."""
+    a = ins.tiny(seed=41, N=5, n_v=9, n_s=6, n_t=12, n_m=1, light=True)
+    a["tm_grid"] = (0.0, 0.0, 1)
+    a["theta"][4] = 0.0
+    r = oracle.solve(a)
+    J = r["J"]
+    assert np.array_equal(J, np.repeat(J[:, :, :1, :], a["soc_grid"][2], axis=2))
+    b = ins.tiny(seed=42, N=5, n_v=9, n_s=6, n_t=40, light=False, t_f=400.0)
+    r = oracle.solve(b)
+    J = r["J"]
+    early = J[:, :, :, :10]
+    fin = early[:, :, :, :1] < JINF
+    d = np.abs(early - early[:, :, :, :1])
+    assert np.all(d[np.broadcast_to(fin, d.shape)] <= 1e-11 * np.abs(early[np.broadcast_to(fin, d.shape)]))
+
+
+# ------------------------------------------------------------- derivatives --
+
+def _policy_stable(inst, th, h, p):
+    tp = list(th); tp[p] += h
+    tm = list(th); tm[p] -= h
+    rp = oracle.solve(ins.with_theta(inst, tp))
+    rm = oracle.solve(ins.with_theta(inst, tm))
+    r0 = oracle.solve(ins.with_theta(inst, th))
+    a0 = oracle.adjoint(ins.with_theta(inst, th), r0["J"], r0["pi"], r0["u0"], want_rho=True)
+    ap = oracle.adjoint(ins.with_theta(inst, tp), rp["J"], rp["pi"], rp["u0"], want_rho=True)
+    am = oracle.adjoint(ins.with_theta(inst, tm), rm["J"], rm["pi"], rm["u0"], want_rho=True)
+    supp = [(x["rho"] > 0) for x in (a0, ap, am)]
+    stable = (r0["u0"] == rp["u0"] == rm["u0"] and np.array_equal(supp[0], supp[1])
+              and np.array_equal(supp[0], supp[2])
+              and np.array_equal(r0["pi"][supp[0][:-1]], rp["pi"][supp[0][:-1]])
+              and np.array_equal(r0["pi"][supp[0][:-1]], rm["pi"][supp[0][:-1]]))
+    return stable, (rp["V0"] - rm["V0"]) / (2 * h)
+
+
+def test_tangent_adjoint_fd_and_identities():
+    """Fixed-policy derivative of V_0: the backward tangent sweep and the
+    forward occupancy sweep agree; dV/dw_t is the expected total time and
+    dV/dw_soc the expected terminal (xi - xi_ref)^2; the occupancy sums to one
+    and reproduces V_0; central finite differences of fresh solves agree at
+    policy-stable points."""
+    inst = ins.plain()
+    r = oracle.solve(inst)
+    tg = oracle.tangent(inst, r["J"], r["pi"], r["u0"])
+    ad = oracle.adjoint(inst, r["J"], r["pi"], r["u0"])
+    np.testing.assert_allclose(tg, ad["grad"], rtol=1e-10)
+    assert ad["grad"][3] == pytest.approx(ad["exp_time"], rel=1e-10)
+    assert ad["grad"][4] == pytest.approx(ad["exp_socpen"], rel=1e-10, abs=1e-15)
+    live = ad["rho_sum"] + np.concatenate([[0.0], np.cumsum(ad["absorbed"])[:-1]])
+    np.testing.assert_allclose(live, 1.0, rtol=1e-12)
+    assert ad["exp_cost"].sum() == pytest.approx(r["V0"], rel=1e-10)
+    # central differences with step 1e-4 |theta_p|, shrunk by 10x (down to
+    # 1e-6) until no argmin on the occupancy support changes between the two
+    # perturbed solves; then fresh-solve differences must equal the tangent
+    checked = 0
+    for p in range(5):
+        for rel in (1e-4, 1e-5, 1e-6):
+            h = rel * abs(inst["theta"][p])
+            stable, fd = _policy_stable(inst, inst["theta"], h, p)
+            if stable:
+                assert fd == pytest.approx(tg[p], rel=1e-6, abs=1e-12), (p, rel)
+                checked += 1
+                break
+    assert checked == 5
+
+
+# ---------------------------------------------------------------- rollout --
+
+def test_rollout_tracks_value():
+    """Following the stored policy from x0 with exact dynamics realises a
+    cost close to V_0 (interpolation error only), with no constraint
+    violation, and the gap shrinks when the grids are refined."""
+    inst = ins.plain()
+    gaps = []
+    for f in (1, 2):
+        x = dict(inst)
+        x["v_grid"] = (0.0, 20.0, 20 * f + 1)
+        x["soc_grid"] = (0.4, 0.7, 10 * f + 1)
+        x["t_grid"] = (0.0, 90.0, 30 * f + 1)
+        r = oracle.solve(x)
+        ro = oracle.rollout(x, r["pi"], r["u0"])
+        assert ro["status"] == 0
+        assert ro["violations"] == 0
+        tr = ro["traj"]
+        assert tr[-1, 2] <= 90.0
+        gaps.append(abs(tr[-1, 7] - r["V0"]) / r["V0"])
+    assert gaps[0] < 0.1
+    assert gaps[1] < gaps[0]
+
+
+# -------------------------------------------------------------- workload --
+
+def test_paper_workload_count():
+    """Sec. IV: grid (35, 26, 40, 23, 30) gives an innermost loop 'on the
+    order of 10^7' per recursion step, 20 steps per solve."""
+    with open(os.path.join(GOLDEN, "paper_grid.json")) as f:
+        g = json.load(f)
+    inst = ins.paper_shape()
+    assert (inst["v_grid"][2], inst["soc_grid"][2], inst["t_grid"][2],
+            inst["te_grid"][2], inst["tm_grid"][2]) == tuple(g["grid"])
+    assert inst["N"] == g["steps_per_solve"]
+    per_step = oracle.count_evals(inst) // inst["N"]
+    assert per_step == int(np.prod(g["grid"]))
+    assert 10 ** g["order_of_magnitude"] <= per_step < 10 ** (g["order_of_magnitude"] + 1)
+    assert per_step == ins.evaluations(inst) // inst["N"]
+
+
+def test_tie_break_lowest_control_index():
+    """Equal candidate values keep the first control scanned (lowest
+    u = a*n_m + b): duplicated engine-torque grid points give exact ties."""
+    inst = ins.tiny(seed=51, N=3, n_v=7, n_s=5, n_t=9, n_e=2, n_m=3, light=False)
+    inst["te_grid"] = (60.0, 60.0, 2)      # both engine-torque indices are 60 Nm
+    r = oracle.solve(inst)
+    pi = r["pi"]
+    assert np.all(pi[pi >= 0] < 3)          # never the duplicate a = 1
+    assert (pi >= 0).sum() > 50
+    assert 0 <= r["u0"] < 3
+
+
+def test_red_phase_half_open():
+    """The red phase is the half-open interval [offset, offset + red) of each
+    cycle: a node exactly at the red-to-green switch is green, a node exactly
+    at the green-to-red switch is red."""
+    inst = ins.tiny(seed=61, N=4, n_v=6, n_s=4, n_t=9, light=False, t_f=40.0)
+    inst["t0_abs"] = 0.0
+    inst["lights"] = [(2, 30.0, 10.0, 5.0)]   # nodes every 5 s: red on [5, 15) and [35, 45)
+    r = oracle.solve(inst)
+    J2, pi2 = r["J"][2], r["pi"][2]
+    for m, t in enumerate(np.arange(9) * 5.0):
+        red = (5.0 <= t < 15.0) or (35.0 <= t < 45.0)
+        if red:
+            assert np.all(J2[1:, :, m] == JINF)
+        else:
+            assert np.any(pi2[1:, :, m] >= 0), t
+    assert np.any(pi2[1:, :, 3] >= 0)   # t = 15 s, the switch to green
+
+
+def test_fuel_map_monomials():
+    """The fuel rate is the polynomial q0 + q1 v + q2 T + q3 v^2 + q4 v T +
+    q5 T^2 (g/s) with the engine on: each unit coefficient vector must give
+    its own monomial, and the stage cost is (mf + w_t) dt."""
+    inst = ins.tiny(seed=5, N=3, light=False)
+    v, Te = 7.0, 75.0                       # a = 1 on the engine grid [0, 150] x 3
+    mono = [1.0, v, Te, v * v, v * Te, Te * Te]
+    for q in range(6):
+        x = dict(inst)
+        x["fuel"] = [1.0 if p == q else 0.0 for p in range(6)]
+        st, o = oracle.transition(x, 0, v, 0.5, 1, 1)
+        assert o["mf"] == pytest.approx(mono[q], rel=1e-15)
+        assert o["cost"] == pytest.approx((mono[q] + x["theta"][3]) * o["dt"], rel=1e-14)
