@@ -1,0 +1,159 @@
+/*
+ * ecodp.h - C ABI of the MI355X (gfx950) dynamic-programming eco-driving solver.
+ *
+ * The library solves the receding-horizon optimal control problem of Zhu et
+ * al., "A GPU Implementation of a Look-Ahead Optimal Controller for Eco-Driving
+ * Based on Dynamic Programming" (ECC 2021), Sec. III: states x = (speed v,
+ * battery SoC xi, travel time t) (Eq. 4a), controls u = (engine torque,
+ * BSG/motor torque) (Eq. 4b), dynamics Eq. 5a-c, stage cost Eq. 1 / Eq. 6,
+ * constraints Eq. 7a-d and the signal feasible-time set Eq. 8, by the backward
+ * recursion Eq. 9a-d on uniform grids with trilinear interpolation of the
+ * next-stage cost-to-go.  Infeasible states and state-control pairs carry the
+ * large finite cost J_inf of Sec. IV (konst[13]); every stored cost-to-go is
+ * at most J_inf.
+ *
+ * Conventions for every entry point:
+ *  - All functions return an int status: DP_OK (0) or a negative DP_E* code.
+ *    Nothing throws across the ABI.  dp_last_error() gives a message for the
+ *    last failure on the calling thread.
+ *  - Argument validation errors are returned synchronously, before any work
+ *    is enqueued.  Work is enqueued asynchronously on the HIP stream given as
+ *    `stream` (a hipStream_t; NULL = the default stream); device faults show up
+ *    as DP_EDEVICE at a later call or at stream synchronisation.
+ *  - Buffers named *_dev and the J / pi / scratch buffers are DEVICE memory
+ *    owned by the caller, borrowed until the enqueued work completes.  Sizes
+ *    come from dp_workspace_size(); per-instance offsets from dp_instance_info().
+ *    The plan owns only host metadata and a small device parameter block.
+ *  - A plan must not be used from two host threads at once.
+ *
+ * Data layouts (all row-major, travel time fastest):
+ *  - value slab J_k: float [n_v][n_soc][n_t]; policy slab pi_k: int16 [n_v][n_soc][n_t]
+ *    holding u = a*n_tm + b (a engine-torque index, b motor-torque index),
+ *    -1 = no control beats J_inf, -2 = wait for green at a red signal (Eq. 5c).
+ *  - J buffer, per instance: (N+1) slabs J_0..J_N when DP_STORE_ALL_V is set,
+ *    else 2 slabs used alternately (J_k in slab k % 2; J_0 ends in slab 0).
+ *  - pi buffer, per instance: N slabs pi_0..pi_{N-1}.
+ */
+#ifndef ECODP_H
+#define ECODP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DP_OK = 0,
+    DP_EINVAL = -1,        /* invalid argument (NaN, bad grid, bad index, ...) */
+    DP_ENOMEM = -2,        /* host or device allocation failed */
+    DP_EDEVICE = -3,       /* no usable device, or a HIP runtime error */
+    DP_EINFEASIBLE = -4,   /* rollout: no admissible control from the current state */
+    DP_ESTATE = -5,        /* call out of order (e.g. adjoint without stored values) */
+    DP_EUNSUPPORTED = -6   /* size or option outside what this build supports */
+};
+
+/* dp_problem_desc.flags */
+#define DP_WAIT_AT_RED 1u      /* a stopped vehicle at a red signal waits for green (Eq. 5c) */
+
+/* dp_options.flags */
+#define DP_STORE_ALL_V 1u      /* keep J_0..J_N (needed by dp_adjoint and for inspection) */
+#define DP_TIMING 2u           /* time every state-sweep launch with HIP events */
+
+/* One receding-horizon problem (Eq. 6-8).  Host pointers; copied at build. */
+typedef struct {
+    int32_t n_stages;          /* N >= 1 steps of ds metres                                     */
+    double ds;                 /* distance step Delta d [m] (Eq. 2)                              */
+    const double *grade;       /* [N] slope (rise/run) of step k -> k+1                          */
+    const double *v_max;       /* [N+1] route speed limit at stage k [m/s] (Eq. 7a); NULL = v_hi  */
+    int32_t n_lights;          /* signals on the horizon                                          */
+    const int32_t *light_stage;/* [n_lights] distinct stages in [1, N-1]                           */
+    const double *light_cycle; /* [n_lights] cycle C [s]                                           */
+    const double *light_red;   /* [n_lights] red duration R in (0, C] [s]                          */
+    const double *light_offset;/* [n_lights] offset O [s]: red iff (t_abs - O) mod C in [0, R)     */
+    double t0_abs;             /* absolute clock at the horizon start [s]                          */
+    double v0, soc0;           /* initial state x0 = (v0, soc0, t = 0), need not be a grid node    */
+    double v_lo, v_hi; int32_t n_v;      /* speed grid, inclusive, v_lo >= 0, n_v >= 2             */
+    double soc_lo, soc_hi; int32_t n_soc;/* SoC grid, n_soc >= 2                                   */
+    double t_f; int32_t n_t;             /* travel-time grid [0, t_f], n_t >= 2                    */
+    double te_lo, te_hi; int32_t n_te;   /* engine torque grid [Nm], n_te >= 1 (lo == hi if 1)     */
+    double tm_lo, tm_hi; int32_t n_tm;   /* BSG torque grid [Nm], n_tm >= 1                         */
+    double theta[5];           /* M [kg], CdA [m^2], Crr, w_t [g/s], w_soc [g]                     */
+    double konst[16];          /* g, rho_air, r_w, i_g, eta_dl, eta_m, C_nom [C], Voc0, Voc1 [V],
+                                  R [ohm], a_min, a_max [m/s^2], xi_ref, J_inf, 0, 0               */
+    double fuel[6];            /* fuel rate q0 + q1 v + q2 T + q3 v^2 + q4 v T + q5 T^2 [g/s], T > 0 */
+    const float *terminal_V;   /* optional [n_v][n_soc][n_t] added to the terminal cost; NULL = none */
+    uint32_t flags;            /* DP_WAIT_AT_RED */
+} dp_problem_desc;
+
+typedef struct {
+    uint32_t flags;            /* DP_STORE_ALL_V | DP_TIMING                                       */
+    int32_t kernel;            /* 0 = automatic choice of the state-sweep variant                  */
+    int32_t tile[4];           /* 0 = automatic; tile[0] = SoC rows per workgroup                  */
+} dp_options;
+
+typedef struct dp_plan dp_plan;
+
+typedef struct {
+    int32_t n_stages, n_v, n_soc, n_t, n_u;
+    size_t J_offset;           /* byte offset of the instance's value slabs in the J buffer        */
+    size_t pi_offset;          /* byte offset of its policy slabs in the pi buffer                 */
+    size_t traj_offset;        /* element (double) offset of its rollout rows in traj_dev          */
+    size_t slab_elems;         /* n_v * n_soc * n_t                                                */
+    int64_t evaluations;       /* N * slab_elems * n_u (dense state-control evaluations)           */
+} dp_instance_info;
+
+/* Validate n_inst problem descriptions, precompute host-side tables in FP64
+ * (grade trigonometry, speed limits, signal red masks and wait times) and
+ * upload them to `device`.  On success *out owns the plan (dp_destroy). */
+int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_options *opt,
+                     int device, dp_plan **out);
+
+/* Bytes the caller must provide for the J, pi and scratch buffers of dp_solve,
+ * dp_rollout and dp_adjoint (all instances of the plan). */
+int dp_workspace_size(const dp_plan *p, size_t *bytes_J, size_t *bytes_pi, size_t *bytes_scratch);
+
+int dp_instance_info_get(const dp_plan *p, int32_t inst, dp_instance_info *info);
+
+/* Backward recursion Eq. 9a-d for every instance: J_N (Eq. 9a), then for
+ * k = N-1..0 the stage table and the state sweep (min and argmin over all
+ * controls at every node), then the exact first step at x0 (Eq. 6):
+ * V0_dev[inst] = min(J_inf, min_u c + interp J_1), u0_dev[inst] = argmin or -1. */
+int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev,
+             void *stream);
+
+/* One backward step k of instance `inst` from a caller-provided J_{k+1} slab
+ * (device float [n_v][n_soc][n_t]) into J_out / pi_out (device slabs). */
+int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_out,
+             int16_t *pi_out, void *scratch, void *stream);
+
+/* Forward rollout of the stored policy from x0 with exact FP64 dynamics.
+ * traj_dev: double rows [v, xi, t, u, T_eng, T_mot, fuel_g, cost] for stages
+ * 0..N of every instance (offset dp_instance_info.traj_offset); the last row's
+ * cost includes the terminal cost.  status_dev[2*inst] = DP_OK or
+ * DP_EINFEASIBLE, status_dev[2*inst+1] = count of exact-state constraint
+ * violations (red crossing, speed limit, leaving the grid). */
+int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_dev,
+               int32_t *status_dev, void *stream);
+
+/* Fixed-policy derivative dV_0/dtheta, theta = (M, CdA, Crr, w_t, w_soc), by
+ * a forward sweep of the occupancy measure (the transpose of the
+ * interpolation) over the stored J_0..J_N and pi.  Requires DP_STORE_ALL_V.
+ * grad_dev: double [n_inst][5]. */
+int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
+               void *scratch, double *grad_dev, void *stream);
+
+/* With DP_TIMING: total device milliseconds and launch count of the state
+ * sweep kernel over every dp_solve / dp_stage since the previous call
+ * (synchronises on the recorded events, then starts a new count). */
+int dp_sweep_time(dp_plan *p, double *ms, int32_t *launches);
+
+void dp_destroy(dp_plan *p);
+const char *dp_status_string(int code);
+int dp_last_error(char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

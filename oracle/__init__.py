@@ -66,6 +66,7 @@ def _load():
     lib.or_stage.argtypes = [ins, C.c_int, d, d, i16, d]
     lib.or_node_q.argtypes = [ins, C.c_int, d, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.or_node_q.restype = C.c_double
+    lib.or_node.argtypes = [ins, C.c_int, d, C.c_int, C.c_int, C.c_int, d, i32, d]
     lib.or_terminal.argtypes = [ins, d]
     lib.or_root.argtypes = [ins, d, d, i32, d]
     lib.or_solve.argtypes = [ins, d, i16, d, d, i32]
@@ -180,6 +181,18 @@ def node_q(inst, k, Jn, i, j, m, u):
     I = _as_inst(inst)
     Jn = np.ascontiguousarray(Jn, dtype=np.float64).ravel()
     return _load().or_node_q(I.ref, int(k), _ptr(Jn, C.c_double), int(i), int(j), int(m), int(u))
+
+
+def node(inst, k, Jn, i, j, m):
+    """One node of the backward step from J_{k+1}: (J_k, pi_k, second best)."""
+    I = _as_inst(inst)
+    Jn = np.ascontiguousarray(Jn, dtype=np.float64).ravel()
+    J = C.c_double()
+    pi = C.c_int32()
+    q2 = C.c_double()
+    _load().or_node(I.ref, int(k), _ptr(Jn, C.c_double), int(i), int(j), int(m),
+                    C.byref(J), C.byref(pi), C.byref(q2))
+    return J.value, pi.value, q2.value
 
 
 def root(inst, J1):

@@ -289,6 +289,7 @@ static succ_t successor_vs(const or_inst *I, const steps_t *h, const pt_t *p, do
 
 static int successor_t(const or_inst *I, const steps_t *h, const pt_t *p, int m0, succ_t *o)
 {
+    if (!(p->dt / h->ht < I->n_t)) return 0;   /* beyond t_f from any node */
     o->t = cf_shift(m0, p->dt / h->ht, I->n_t);
     return cf_in_range(o->t, I->n_t);
 }
@@ -325,6 +326,38 @@ double or_node_q(const or_inst *I, int k, const double *Jn, int i, int j, int m,
     succ_t sc = successor(I, &h, &p, xi, (double)j, m);
     if (!sc.ok) return Jinf;
     return p.cost + interp_cf(I, Jn, sc.v, sc.s, sc.t);
+}
+
+/* One node of Eq. 9b-d: J_k, pi_k and the second-best candidate, from J_{k+1}
+ * (the same rule as the stage sweep, evaluated for a single node). */
+void or_node(const or_inst *I, int k, const double *Jn, int i, int j, int m,
+             double *Jout, int32_t *piout, double *q2out)
+{
+    const int nu = I->n_e * I->n_m;
+    const double Jinf = I->konst[K_JINF];
+    const int L = light_at(I, k);
+    const double v = grid_val(I->v_lo, I->v_hi, I->n_v, i);
+    double best = Jinf, second = Jinf;
+    int bu = -1;
+    double phase = 0.0;
+    int red = L >= 0 && is_red(I, L, grid_val(0.0, I->t_f, I->n_t, m), &phase);
+    if (v > I->vmax[k]) {
+        /* infeasible node */
+    } else if (red) {
+        if (v == 0.0 && I->wait_at_red) {
+            double val = or_node_q(I, k, Jn, i, j, m, -2);
+            if (val < best) { best = val; bu = -2; }
+        }
+    } else {
+        for (int u = 0; u < nu; u++) {
+            double Q = or_node_q(I, k, Jn, i, j, m, u);
+            if (Q < best) { second = best; best = Q; bu = u; }
+            else if (Q < second) second = Q;
+        }
+    }
+    *Jout = best;
+    *piout = bu;
+    *q2out = second;
 }
 
 /* --------------------------------------------------------------- terminal -- */

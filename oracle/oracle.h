@@ -64,6 +64,10 @@ void or_stage(const or_inst *I, int k, const double *Jn, double *Jk, int16_t *pi
 /* Value of one node for one control (index a*n_m+b), or the WAIT value for u = -2. */
 double or_node_q(const or_inst *I, int k, const double *Jn, int i, int j, int m, int u);
 
+/* One node of the backward step: J_k, pi_k and the second-best value. */
+void or_node(const or_inst *I, int k, const double *Jn, int i, int j, int m,
+             double *Jout, int32_t *piout, double *q2out);
+
 /* Terminal slab J_N (Eq. 9a). */
 void or_terminal(const or_inst *I, double *JN);
 

@@ -1,0 +1,425 @@
+// FP64 kernels that follow the stored policy: the forward rollout from x0 and
+// the fixed-policy adjoint dV_0/dtheta (forward sweep of the occupancy
+// measure, i.e. the transpose of the trilinear interpolation, stage by stage).
+#include "dp_internal.h"
+
+namespace ecodp {
+
+__device__ inline bool red_at(const DevInst &P, int L, double t_rel, double &phase)
+{
+#pragma clang fp contract(off)
+    double x = fmod(P.t0_abs + t_rel - P.l_off[L], P.l_cycle[L]);
+    if (x < 0.0) x += P.l_cycle[L];
+    phase = x;
+    return x < P.l_red[L];
+}
+
+// Control at an off-grid state: among the bracketing nodes with positive
+// weight and a stored control (>= 0), the largest weight; equal weights go to
+// the lowest linear node index; -1 if none.
+__device__ int policy_lookup(const DevInst &P, const int16_t *pik, double v, double xi, double t, int &oog)
+{
+#pragma clang fp contract(off)
+    double r[3] = {(v - P.v_lo) / P.hv, (xi - P.s_lo) / P.hs, t / P.ht};
+    const int n[3] = {P.n_v, P.n_s, P.n_t};
+    int c[3];
+    double f[3];
+    for (int d = 0; d < 3; d++) {
+        if (r[d] < 0.0) {
+            r[d] = 0.0;
+            oog = 1;
+        }
+        if (r[d] > n[d] - 1) {
+            r[d] = n[d] - 1;
+            oog = 1;
+        }
+        cell_of(r[d], n[d], c[d], f[d]);
+    }
+    double bw = -1.0;
+    long bn = -1;
+    int bu = -1;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int e = 0; e < 2; e++) {
+                const double w = (a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1]) * (e ? f[2] : 1.0 - f[2]);
+                if (!(w > 0.0)) continue;
+                const long nidx = ((long)(c[0] + a) * P.n_s + (c[1] + b)) * P.n_t + (c[2] + e);
+                const int u = pik[nidx];
+                if (u < 0) continue;
+                if (w > bw || (w == bw && nidx < bn)) {
+                    bw = w;
+                    bn = nidx;
+                    bu = u;
+                }
+            }
+    return bu;
+}
+
+__device__ double interp_f64(const DevInst &P, const float *J, double rv, double rs, double rt)
+{
+#pragma clang fp contract(off)
+    int c[3];
+    double f[3];
+    cell_of(rv, P.n_v, c[0], f[0]);
+    cell_of(rs, P.n_s, c[1], f[1]);
+    cell_of(rt, P.n_t, c[2], f[2]);
+    double acc = 0.0;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int e = 0; e < 2; e++) {
+                const double w = (a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1]) * (e ? f[2] : 1.0 - f[2]);
+                if (!(w > 0.0)) continue;
+                acc += w * (double)J[((long)(c[0] + a) * P.n_s + (c[1] + b)) * P.n_t + (c[2] + e)];
+            }
+    return acc;
+}
+
+// One thread per instance: x0, the root control u_0*, then at each stage the
+// nearest stored control (or the wait at a red signal), exact FP64 dynamics,
+// fuel, time and cost accumulated in FP64, terminal cost at N.
+__global__ void k_rollout(DevInst P, const int16_t *__restrict__ pi, const int16_t *__restrict__ u0p,
+                          double *__restrict__ traj, int32_t *__restrict__ status)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const long S = (long)P.n_v * P.n_s * P.n_t;
+    double v = P.v0, xi = P.soc0, t = 0.0, fuel = 0.0, cost = 0.0;
+    int st = 0, viol = 0;
+    const double nan = __builtin_nan("");
+    for (int r = 0; r <= P.N; r++)
+        for (int c = 0; c < 8; c++) traj[r * 8 + c] = nan;
+    for (int k = 0; k < P.N; k++) {
+        double *row = traj + k * 8;
+        row[0] = v;
+        row[1] = xi;
+        row[2] = t;
+        row[6] = fuel;
+        row[7] = cost;
+        int u;
+        if (k == 0) {
+            u = *u0p;
+            if (v > P.vmax[0]) viol++;
+        } else {
+            const int L = P.light_of_stage[k];
+            double phase;
+            if (L >= 0 && red_at(P, L, t, phase)) {
+                if (v == 0.0 && P.wait) {
+                    const double tau = P.l_red[L] - phase;
+                    row[3] = -2.0;
+                    t += tau;
+                    cost += P.wt * tau;
+                    continue;
+                }
+                viol++;
+            }
+            if (v > P.vmax[k]) viol++;
+            int oog = 0;
+            u = policy_lookup(P, pi + (long)k * S, v, xi, t, oog);
+            if (oog) viol++;
+        }
+        if (u < 0) {
+            st = -4;
+            break;
+        }
+        const int a = u / P.n_m, b = u % P.n_m;
+        row[3] = u;
+        row[4] = P.e_lo + a * P.he;
+        row[5] = P.m_lo + b * P.hm;
+        const PT p = powertrain(P, k, v, a, b);
+        double I;
+        const bool bok = battery_current(P, p.Pb, xi, I);
+        if ((p.st & 4) || !bok) {
+            st = -4;
+            break;
+        }
+        if (p.st) viol++;
+        fuel += p.mf * p.dt;
+        cost += p.cost;
+        xi = xi - p.dt * I / P.Cnom;
+        v = p.v1;
+        t = t + p.dt;
+        if (xi < P.s_lo || xi > P.s_hi || t > P.t_f) viol++;
+    }
+    if (st == 0) {
+        double *row = traj + P.N * 8;
+        if (v > P.vmax[P.N]) viol++;
+        double pen = P.wsoc * (xi - P.xiref) * (xi - P.xiref);
+        if (P.terminal_V) {
+            double r[3] = {(v - P.v_lo) / P.hv, (xi - P.s_lo) / P.hs, t / P.ht};
+            const int n[3] = {P.n_v, P.n_s, P.n_t};
+            for (int d = 0; d < 3; d++) r[d] = r[d] < 0.0 ? 0.0 : (r[d] > n[d] - 1 ? n[d] - 1 : r[d]);
+            pen += interp_f64(P, P.terminal_V, r[0], r[1], r[2]);
+        }
+        cost += pen;
+        row[0] = v;
+        row[1] = xi;
+        row[2] = t;
+        row[6] = fuel;
+        row[7] = cost;
+    }
+    status[0] = st;
+    status[1] = viol;
+}
+
+// ------------------------------------------------------------------ adjoint --
+
+struct Cells {
+    int c[3];
+    double f[3];
+};
+
+// Partial derivatives with the control fixed of the stage cost and of the
+// three index coordinates of the successor with respect to theta = (M, CdA,
+// Crr, w_t, w_soc), from q = v^2 + 2 dd (F_tr - F_road)/M, v1 = sqrt(q),
+// dt = 2 dd/(v + v1), SoC shift -dt I/(C_nom h_s), time shift dt/h_t.
+__device__ void step_partials(const DevInst &P, double v, const PT &p, double I, double dc[5], double dr[5][3])
+{
+#pragma clang fp contract(off)
+    double dq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    dq[0] = 2.0 * P.ds * (-P.g * (P.Crr * p.cosa + p.sina) / P.M - (p.Ftr - p.Froad) / (P.M * P.M));
+    dq[1] = -P.ds * P.rho * v * v / P.M;
+    dq[2] = -2.0 * P.ds * P.g * p.cosa;
+    for (int q = 0; q < 5; q++) {
+        const double dv1 = p.q > 0.0 ? dq[q] / (2.0 * p.v1) : 0.0;
+        const double vs = v + p.v1;
+        const double ddt = -2.0 * P.ds / (vs * vs) * dv1;
+        dc[q] = (p.mf + P.wt) * ddt + (q == 3 ? p.dt : 0.0);
+        dr[q][0] = dv1 / P.hv;
+        dr[q][1] = -(I / (P.Cnom * P.hs)) * ddt;
+        dr[q][2] = ddt / P.ht;
+    }
+}
+
+// Derivatives of the trilinear interpolant along each index coordinate inside
+// the cell; a coordinate exactly on a grid plane (f = 0 or 1) contributes 0.
+__device__ void interp_grad(const DevInst &P, const float *J, const Cells &x, double g[3])
+{
+#pragma clang fp contract(off)
+    for (int d = 0; d < 3; d++) {
+        g[d] = 0.0;
+        if (!(x.f[d] > 0.0 && x.f[d] < 1.0)) continue;
+        double acc = 0.0;
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int e = 0; e < 2; e++) {
+                    const int bits[3] = {a, b, e};
+                    double w = 1.0;
+                    bool skip = false;
+                    for (int o = 0; o < 3; o++) {
+                        if (o == d) continue;
+                        const double wo = bits[o] ? x.f[o] : 1.0 - x.f[o];
+                        if (!(wo > 0.0)) {
+                            skip = true;
+                            break;
+                        }
+                        w *= wo;
+                    }
+                    if (skip) continue;
+                    const double Jc =
+                        (double)J[((long)(x.c[0] + a) * P.n_s + (x.c[1] + b)) * P.n_t + (x.c[2] + e)];
+                    acc += (bits[d] ? 1.0 : -1.0) * w * Jc;
+                }
+        g[d] = acc;
+    }
+}
+
+__device__ void scatter(const DevInst &P, double *rho_next, double r, const Cells &x, bool atomic)
+{
+#pragma clang fp contract(off)
+    for (int a = 0; a < 2; a++) {
+        const double wa = a ? x.f[0] : 1.0 - x.f[0];
+        if (!(wa > 0.0)) continue;
+        for (int b = 0; b < 2; b++) {
+            const double wb = b ? x.f[1] : 1.0 - x.f[1];
+            if (!(wb > 0.0)) continue;
+            for (int e = 0; e < 2; e++) {
+                const double we = e ? x.f[2] : 1.0 - x.f[2];
+                if (!(we > 0.0)) continue;
+                double *dst = rho_next + ((long)(x.c[0] + a) * P.n_s + (x.c[1] + b)) * P.n_t + (x.c[2] + e);
+                const double add = r * wa * wb * we;
+                if (atomic)
+                    unsafeAtomicAdd(dst, add);
+                else
+                    *dst += add;
+            }
+        }
+    }
+}
+
+// Successor cells of a state at speed v, SoC xi with index coordinate rs0 and
+// time node m0 under control u; false if the pair is infeasible.
+__device__ bool successor_cells(const DevInst &P, int k, double v, double xi, double rs0, int m0, int u, PT &p,
+                                double &I, Cells &x)
+{
+#pragma clang fp contract(off)
+    p = powertrain(P, k, v, u / P.n_m, u % P.n_m);
+    if (p.st) return false;
+    if (!battery_current(P, p.Pb, xi, I)) return false;
+    const double rv = (p.v1 - P.v_lo) / P.hv;
+    if (!(rv >= 0.0 && rv <= P.n_v - 1)) return false;
+    const double rs = rs0 - (p.dt * I) / (P.Cnom * P.hs);
+    if (!(rs >= 0.0 && rs <= P.n_s - 1)) return false;
+    const double delta = p.dt / P.ht;
+    if (!(delta < P.n_t)) return false;
+    cell_of(rv, P.n_v, x.c[0], x.f[0]);
+    cell_of(rs, P.n_s, x.c[1], x.f[1]);
+    const double fl = floor(delta);
+    int tc = m0 + (int)fl;
+    double ft = delta - fl;
+    if (tc > P.n_t - 2) {
+        ft += (double)(tc - (P.n_t - 2));
+        tc = P.n_t - 2;
+        if (ft > 1.0) return false;
+    }
+    x.c[2] = tc;
+    x.f[2] = ft;
+    return true;
+}
+
+__global__ void k_adj_root(DevInst P, const float *__restrict__ J1, const int16_t *__restrict__ u0p,
+                           double *__restrict__ rho1, double *__restrict__ gacc)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int u0 = *u0p;
+    const double nan = __builtin_nan("");
+    PT p;
+    double I;
+    Cells x;
+    const double rs0 = (P.soc0 - P.s_lo) / P.hs;
+    if (u0 < 0 || !successor_cells(P, 0, P.v0, P.soc0, rs0, 0, u0, p, I, x)) {
+        for (int q = 0; q < 5; q++) gacc[q] = nan;
+        return;
+    }
+    double dc[5], dr[5][3], gJ[3];
+    step_partials(P, P.v0, p, I, dc, dr);
+    interp_grad(P, J1, x, gJ);
+    for (int q = 0; q < 5; q++) gacc[q] += dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2];
+    scatter(P, rho1, 1.0, x, false);
+}
+
+__device__ inline void block_add5(double g[5], double *gacc)
+{
+    __shared__ double red[5][256];
+    for (int q = 0; q < 5; q++) red[q][threadIdx.x] = g[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < 5; q++) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 5; q++)
+            if (red[q][0] != 0.0) unsafeAtomicAdd(&gacc[q], red[q][0]);
+}
+
+// Stage k >= 1: every node with occupancy rho > 0 follows its stored control:
+// gradient terms weighted by rho, and rho times the interpolation weights
+// added to the stage k+1 occupancy.  Wait nodes add rho * tau to dV/dw_t and
+// move in time only.  Nodes without a control keep J_inf and stop the mass.
+__global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
+                                                   const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
+                                                   const double *__restrict__ rho, double *__restrict__ rho_next,
+                                                   double *__restrict__ gacc)
+{
+#pragma clang fp contract(off)
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const long S = (long)P.n_v * P.n_s * P.n_t;
+    for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
+        const double r = rho[n];
+        if (!(r > 0.0)) continue;
+        const int m = (int)(n % P.n_t);
+        const long ij = n / P.n_t;
+        const int j = (int)(ij % P.n_s);
+        const int i = (int)(ij / P.n_s);
+        const int u = pik[n];
+        if (u == -2) {
+            const TLEntry e = tl[m];
+            g[3] += r * e.tau;
+            const long base = ((long)i * P.n_s + j) * P.n_t;
+            if (1.0 - e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc], r * (1.0 - e.wf));
+            if (e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc + 1], r * e.wf);
+        } else if (u >= 0) {
+            PT p;
+            double I;
+            Cells x;
+            const double v = P.v_lo + i * P.hv;
+            const double xi = P.s_lo + j * P.hs;
+            if (!successor_cells(P, k, v, xi, (double)j, m, u, p, I, x)) continue;
+            double dc[5], dr[5][3], gJ[3];
+            step_partials(P, v, p, I, dc, dr);
+            interp_grad(P, Jn, x, gJ);
+            for (int q = 0; q < 5; q++) g[q] += r * (dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2]);
+            scatter(P, rho_next, r, x, true);
+        }
+    }
+    block_add5(g, gacc);
+}
+
+// Stage N: dV/dw_soc gains rho_N (xi - xi_ref)^2 on nodes below J_inf.
+__global__ void __launch_bounds__(256) k_adj_terminal(DevInst P, const float *__restrict__ JN,
+                                                      const double *__restrict__ rho, double *__restrict__ gacc)
+{
+#pragma clang fp contract(off)
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const long S = (long)P.n_v * P.n_s * P.n_t;
+    const float Jinf = (float)P.Jinf;
+    for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
+        const double r = rho[n];
+        if (!(r > 0.0) || !(JN[n] < Jinf)) continue;
+        const int j = (int)((n / P.n_t) % P.n_s);
+        const double d = P.s_lo + j * P.hs - P.xiref;
+        g[4] += r * d * d;
+    }
+    block_add5(g, gacc);
+}
+
+__global__ void k_fill_f64(double *p, long n, double v)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) p[q] = v;
+}
+
+static int grid_for(long n)
+{
+    long b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, const TLEntry *, double *traj,
+                   int32_t *status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rollout, dim3(1), dim3(64), 0, s, P, pi, u0, traj, status);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill_f64(double *p, long n, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_root, dim3(1), dim3(64), 0, s, P, J1, u0, rho1, gacc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
+                         const double *rho, double *rho_next, double *gacc, hipStream_t s)
+{
+    const long S = (long)P.n_v * P.n_s * P.n_t;
+    hipLaunchKernelGGL(k_adj_stage, dim3(grid_for(S)), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_adjoint_terminal(const DevInst &P, const float *JN, const double *rho, double *gacc, hipStream_t s)
+{
+    const long S = (long)P.n_v * P.n_s * P.n_t;
+    hipLaunchKernelGGL(k_adj_terminal, dim3(grid_for(S)), dim3(256), 0, s, P, JN, rho, gacc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ecodp

@@ -1,0 +1,25 @@
+// Internal declarations of the ecodp library (host launch wrappers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dp_model.h"
+
+namespace ecodp {
+
+int launch_terminal(const DevInst &P, float *JN, hipStream_t s);
+int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, hipStream_t s);
+int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const StageEntry *st,
+                 const BatEntry *bat, const TLEntry *tl, hipStream_t s);
+int launch_root(const DevInst &P, const float *J1, float *V0, int16_t *u0, hipStream_t s);
+
+int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, const TLEntry *unused,
+                   double *traj, int32_t *status, hipStream_t s);
+int launch_fill_f64(double *p, long n, double v, hipStream_t s);
+int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
+                        hipStream_t s);
+int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
+                         const double *rho, double *rho_next, double *gacc, hipStream_t s);
+int launch_adjoint_terminal(const DevInst &P, const float *JN, const double *rho, double *gacc, hipStream_t s);
+
+}  // namespace ecodp

@@ -1,0 +1,129 @@
+// Device-side problem parameters and the FP64 stage model of the eco-driving
+// DP (Zhu et al., ECC 2021, Sec. III).  Shared by the kernels of this library
+// only; host code fills DevInst once per plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecodp {
+
+// Per-instance constants, passed to kernels by value.
+struct DevInst {
+    int N, n_v, n_s, n_t, n_e, n_m, n_u;
+    int wait;            // DP_WAIT_AT_RED
+    int zero_row;        // index of the v = 0 speed node, or -1
+    double ds;
+    double v_lo, s_lo;
+    double v_hi, s_hi, t_f;
+    double hv, hs, ht, he, hm;
+    double e_lo, m_lo;
+    double M, CdA, Crr, wt, wsoc;
+    double g, rho, rw, ig, eta, etam, Cnom, Voc0, Voc1, Rb, amin, amax, xiref, Jinf;
+    double q[6];
+    double v0, soc0, t0_abs;
+    const double *cosa, *sina;   // [N] grade trigonometry (host FP64)
+    const double *vmax;          // [N+1]
+    const int *light_of_stage;   // [N+1]: signal index at stage k or -1
+    const double *l_cycle, *l_red, *l_off;
+    const float *terminal_V;     // optional
+};
+
+// Compact per-(speed node, control) data of one stage, FP64-derived.
+struct StageEntry {
+    float c;       // stage cost (mf + w_t) dt
+    float fv, gv;  // speed fraction and 1 - fraction (each rounded from FP64)
+    float ft, gt;  // time fraction of the per-step advance dt / h_t
+    int16_t iv;    // lower speed cell in [0, n_v - 2]; -1 = infeasible pair
+    int16_t dtc;   // whole time cells advanced
+};
+
+// Per-(speed node, control, SoC node) battery coordinate.
+struct BatEntry {
+    int32_t jx;    // lower SoC cell in [0, n_s - 2]; -1 = infeasible
+    float fx, gx;
+};
+
+// Per-(signal, time node) data, host FP64.
+struct TLEntry {
+    int32_t red;   // 1 if the node's absolute time is in a red phase
+    int32_t wc;    // wait: lower time cell of t_m + tau; -1 if beyond t_f
+    double wf;     // wait: fraction
+    double tau;    // wait: time to the end of red [s]
+    float wcost;   // w_t * tau rounded to FP32
+    float wf32, wg32;
+    float pad;
+};
+
+// Result of the continuous one-step model for (stage k, speed v, control).
+struct PT {
+    double v1, acc, dt, cost, mf, Pb, q, Ftr, Froad, cosa, sina;
+    int st;        // 1 accel bound, 2 speed limit, 4 zero mean speed
+};
+
+// Eq. 5a (constant force over the step), Eq. 2, Eq. 1 and the BSG power
+// demand.  FP64 without contraction so that cells and feasibility match an
+// IEEE double evaluation of the same expressions.
+__device__ __host__ inline PT powertrain(const DevInst &P, int k, double v, int a, int b)
+{
+#pragma clang fp contract(off)
+    PT p;
+    const double Te = P.e_lo + a * P.he;
+    const double Tm = P.m_lo + b * P.hm;
+    p.cosa = P.cosa[k];
+    p.sina = P.sina[k];
+    p.Ftr = P.eta * (Te + Tm) * P.ig / P.rw;
+    p.Froad = P.M * P.g * (P.Crr * p.cosa + p.sina) + 0.5 * P.rho * P.CdA * v * v;
+    p.q = v * v + 2.0 * P.ds * (p.Ftr - p.Froad) / P.M;
+    p.st = 0;
+    if (p.q > 0.0) {
+        p.v1 = sqrt(p.q);
+        p.acc = (p.Ftr - p.Froad) / P.M;
+    } else {
+        p.v1 = 0.0;                       // stops inside the step
+        p.acc = -v * v / (2.0 * P.ds);
+    }
+    if (p.acc < P.amin || p.acc > P.amax) p.st |= 1;
+    if (p.v1 > P.vmax[k + 1]) p.st |= 2;
+    const double vs = v + p.v1;
+    if (!(vs > 0.0)) {
+        p.st |= 4;
+        p.dt = 1.0e300;
+    } else {
+        p.dt = 2.0 * P.ds / vs;
+    }
+    double mf = 0.0;
+    if (Te != 0.0) {
+        mf = P.q[0] + P.q[1] * v + P.q[2] * Te + P.q[3] * v * v + P.q[4] * v * Te + P.q[5] * Te * Te;
+        if (mf < 0.0) mf = 0.0;
+    }
+    p.mf = mf;
+    p.cost = (mf + P.wt) * p.dt;
+    const double w = v * P.ig / P.rw;
+    const double Pm = Tm * w;
+    p.Pb = Pm >= 0.0 ? Pm / P.etam : Pm * P.etam;
+    return p;
+}
+
+// Zeroth-order battery: the current drawn for power Pb at SoC xi, or false if
+// Pb exceeds Voc^2 / (4R).
+__device__ __host__ inline bool battery_current(const DevInst &P, double Pb, double xi, double &I)
+{
+#pragma clang fp contract(off)
+    const double Voc = P.Voc0 + P.Voc1 * xi;
+    const double D = Voc * Voc - 4.0 * P.Rb * Pb;
+    if (D < 0.0) return false;
+    I = 2.0 * Pb / (Voc + sqrt(D));
+    return true;
+}
+
+// Lower cell and fraction of an index coordinate r in [0, n-1]: c = min(floor r, n-2).
+__device__ __host__ inline void cell_of(double r, int n, int &c, double &f)
+{
+    const double fl = floor(r);
+    c = (int)fl;
+    if (c > n - 2) c = n - 2;
+    f = r - c;
+}
+
+}  // namespace ecodp

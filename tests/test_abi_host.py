@@ -1,0 +1,109 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/ecodp.h declares, validates arguments before it
+touches a device, and reports a missing device as DP_EDEVICE."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2104_01284_amd import _lib as L
+from paper_2104_01284_amd import instances as ins
+from paper_2104_01284_amd.api import _Desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.SO_PATH):
+        from paper_2104_01284_amd import build
+        build.build()
+    return L.load(require_torch=False)
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ecodp.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(dp_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.dp_status_string(code)
+    assert lib.dp_status_string(-99) == b"unknown status"
+
+
+def build_rc(lib, inst, n=1, flags=0):
+    d = _Desc(inst)
+    arr = (L.DpProblemDesc * n)(*([d.d] * n))
+    opt = L.DpOptions()
+    opt.flags = flags
+    h = C.c_void_p()
+    rc = lib.dp_build_problem(arr, n, C.byref(opt), 0, C.byref(h))
+    if rc == 0:
+        lib.dp_destroy(h)
+    return rc
+
+
+def last_error(lib):
+    buf = C.create_string_buffer(512)
+    lib.dp_last_error(buf, 512)
+    return buf.value.decode()
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda x: x.__setitem__("ds", float("nan")), "ds"),
+    (lambda x: x.__setitem__("v_grid", (0.0, 20.0, 1)), "speed grid"),
+    (lambda x: x.__setitem__("soc_grid", (0.7, 0.4, 11)), "SoC grid"),
+    (lambda x: x.__setitem__("t_grid", (0.0, -1.0, 31)), "time grid"),
+    (lambda x: x.__setitem__("lights", [(0, 60.0, 25.0, 10.0)]), "light"),
+    (lambda x: x.__setitem__("lights", [(50, 60.0, 25.0, 10.0)]), "light"),
+    (lambda x: x.__setitem__("lights", [(10, 60.0, 70.0, 10.0)]), "red"),
+    (lambda x: x.__setitem__("lights", [(10, 60.0, 25.0, 0.0), (10, 50.0, 20.0, 0.0)]), "two lights"),
+    (lambda x: x.__setitem__("theta", [0.0, 0.7, 0.01, 0.5, 5000.0]), "theta"),
+    (lambda x: x["konst"].__setitem__(13, 0.0), "constants"),
+    (lambda x: x.__setitem__("soc0", 0.9), "x0"),
+    (lambda x: x.__setitem__("te_grid", (0.0, 150.0, 4000)), "controls"),
+    (lambda x: x.__setitem__("t_grid", (0.0, 90.0, 2000)), "n_t"),
+])
+def test_validation_before_device(lib, mutate, needle):
+    inst = ins.plain()
+    inst["konst"] = list(inst["konst"])
+    mutate(inst)
+    rc = build_rc(lib, inst)
+    assert rc in (L.DP_EINVAL, L.DP_EUNSUPPORTED)
+    assert needle in last_error(lib)
+
+
+def test_nan_grade_rejected(lib):
+    inst = ins.plain()
+    inst["grade"] = np.array(inst["grade"])
+    inst["grade"][7] = np.nan
+    assert build_rc(lib, inst) == L.DP_EINVAL
+    assert "grade[7]" in last_error(lib)
+
+
+def test_null_arguments(lib):
+    h = C.c_void_p()
+    assert lib.dp_build_problem(None, 1, None, 0, C.byref(h)) == L.DP_EINVAL
+    assert lib.dp_build_problem(None, 1, None, 0, None) == L.DP_EINVAL
+    assert lib.dp_solve(None, None, None, None, None, None, None) == L.DP_EINVAL
+    assert lib.dp_rollout(None, None, None, None, None, None) == L.DP_EINVAL
+    assert lib.dp_adjoint(None, None, None, None, None, None, None) == L.DP_EINVAL
+    a = C.c_size_t()
+    assert lib.dp_workspace_size(None, C.byref(a), None, None) == L.DP_EINVAL
+    lib.dp_destroy(None)
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU device node is present")
+def test_no_device_is_edevice(lib):
+    assert build_rc(lib, ins.plain()) == L.DP_EDEVICE

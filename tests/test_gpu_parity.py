@@ -1,0 +1,249 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (FP32 values, FP64 coordinates):
+  * V_0: |V_gpu - V_64| <= 1e-4 |V_64|.
+  * Per-stage isolated step (the same FP32-rounded J_{k+1} fed to both):
+    |J_gpu - J_64| <= 4e-6 max(1, |J_64|); the policy must match except at
+    nodes whose FP64 gap between the best and second-best candidate is below
+    1e-6 max(1, |J_64|) (FP32 resolves about 6e-8 relative, so an absolute
+    1e-6 gap is below its resolution for J > 16 g; the count under the
+    absolute reading is reported too).
+  * Terminal slab: exactly the FP32 rounding of the FP64 value.
+  * Rollout (same policy): FP64 agreement to 1e-9 relative.
+  * Adjoint (same J and policy): FP64 agreement to 1e-9 relative.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_01284_amd import instances as ins
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+REL_J = 4e-6
+REL_GAP = 1e-6
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+def Plan(*a, **k):
+    from paper_2104_01284_amd.api import Plan as P
+    return P(*a, **k)
+
+
+def policy_mismatch(pi_g, pi_o, J_o, q2_o):
+    mism = pi_g != pi_o
+    gap = q2_o - J_o
+    bad = mism & ~(gap < REL_GAP * np.maximum(1.0, np.abs(J_o)))
+    abs_bad = mism & ~(gap < 1e-6)
+    return int(bad.sum()), int(mism.sum()), int(abs_bad.sum())
+
+
+def check_stage_isolated(torch, plan, inst, b, k, Jn32, tag):
+    """Both sides evaluate stage k from the same FP32 slab J_{k+1}."""
+    Jn64 = Jn32.astype(np.float64)
+    Jo, po, q2 = oracle.stage(inst, k, Jn64)
+    Jg, pg = plan.stage(b, k, torch.from_numpy(Jn32).cuda())
+    torch.cuda.synchronize()
+    Jg, pg = Jg.cpu().numpy().astype(np.float64), pg.cpu().numpy()
+    err = np.abs(Jg - Jo) / np.maximum(1.0, np.abs(Jo))
+    assert err.max() <= REL_J, (tag, k, float(err.max()))
+    bad, mism, abs_bad = policy_mismatch(pg, po, Jo, q2)
+    assert bad == 0, (tag, k, bad, mism)
+    return mism, abs_bad
+
+
+def ragged_instances():
+    out = []
+    out.append(ins.tiny(seed=101, N=7, n_v=9, n_s=7, n_t=67, n_e=5, n_m=5, light=True, t_f=90.0))
+    out.append(ins.tiny(seed=102, N=5, n_v=2, n_s=2, n_t=2, n_e=3, n_m=3, light=False, t_f=30.0))
+    x = ins.tiny(seed=103, N=6, n_v=13, n_s=6, n_t=130, n_e=4, n_m=3, light=True, t_f=120.0, wait=False)
+    out.append(x)
+    y = ins.tiny(seed=104, N=4, n_v=8, n_s=5, n_t=33, n_e=3, n_m=3, light=False, t_f=40.0)
+    rng = np.random.default_rng(0)
+    y["terminal_V"] = rng.uniform(0, 20, (8, 5, 33)).astype(np.float32)
+    y["te_grid"] = (30.0, 30.0, 1)
+    out.append(y)
+    z = ins.tiny(seed=105, N=8, n_v=11, n_s=9, n_t=64, n_e=3, n_m=5, light=True, t_f=60.0)
+    z["v_grid"] = (2.0, 20.0, 11)      # no zero-speed row
+    z["v0"] = 8.0
+    out.append(z)
+    return out
+
+
+def test_plain_end_to_end(torch):
+    inst = ins.plain()
+    say("plain_500m end-to-end solve")
+    plan = Plan([inst], store_all=True)
+    V0, u0 = plan.solve()
+    torch.cuda.synchronize()
+    r = oracle.solve(inst, q2=True)
+    Vg = float(V0.cpu()[0])
+    assert abs(Vg - r["V0"]) <= 1e-4 * abs(r["V0"]), (Vg, r["V0"])
+    assert int(u0.cpu()[0]) == r["u0"]
+    J = plan.values(0).cpu().numpy().astype(np.float64)
+    assert np.array_equal(J[-1], r["J"][-1].astype(np.float32).astype(np.float64))
+    err = np.abs(J - r["J"]) / np.maximum(1.0, np.abs(r["J"]))
+    say("max end-to-end relative J error", float(err.max()))
+    assert err.max() < 1e-4
+    pi = plan.policy(0).cpu().numpy()
+    bad, mism, _ = policy_mismatch(pi, r["pi"], r["J"][:-1], r["q2"])
+    say("end-to-end policy mismatches", mism, "outside the near-tie band", bad)
+
+
+def test_plain_stage_isolated_every_stage(torch):
+    inst = ins.plain()
+    r = oracle.solve(inst)
+    plan = Plan([inst])
+    tot = tot_abs = 0
+    for k in range(inst["N"]):
+        say("plain_500m isolated stage", k)
+        m, a = check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), "plain")
+        tot += m
+        tot_abs += a
+    say("isolated mismatches (all in the near-tie band)", tot, "outside an absolute 1e-6 gap", tot_abs)
+
+
+@pytest.mark.parametrize("idx", range(5))
+def test_ragged_and_edge_instances(torch, idx):
+    inst = ragged_instances()[idx]
+    say("edge instance", idx, inst["name"], inst["v_grid"], inst["soc_grid"], inst["t_grid"])
+    r = oracle.solve(inst, q2=True)
+    plan = Plan([inst], store_all=True)
+    V0, u0 = plan.solve()
+    torch.cuda.synchronize()
+    assert abs(float(V0.cpu()[0]) - r["V0"]) <= 1e-4 * abs(r["V0"])
+    J = plan.values(0).cpu().numpy().astype(np.float64)
+    assert np.array_equal(J[-1], r["J"][-1].astype(np.float32).astype(np.float64))
+    for k in range(inst["N"]):
+        check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), inst["name"])
+
+
+def test_rollout_matches_oracle_given_gpu_policy(torch):
+    for inst in [ins.plain()] + ragged_instances()[:1]:
+        say("rollout", inst["name"])
+        plan = Plan([inst], store_all=True)
+        plan.solve()
+        trajs, status = plan.rollout()
+        torch.cuda.synchronize()
+        pi = plan.policy(0).cpu().numpy()
+        u0 = int(plan.u0.cpu()[0])
+        ro = oracle.rollout(inst, pi, u0)
+        st = status.cpu().numpy()[0]
+        assert st[0] == ro["status"] and st[1] == ro["violations"]
+        tg = trajs[0].cpu().numpy()
+        to = ro["traj"]
+        both = np.isfinite(to)
+        assert np.array_equal(np.isfinite(tg), both)
+        np.testing.assert_allclose(tg[both], to[both], rtol=1e-9, atol=1e-9)
+
+
+def test_adjoint_matches_oracle_given_gpu_values(torch):
+    for inst in [ins.plain()] + ragged_instances()[:1]:
+        say("adjoint", inst["name"])
+        plan = Plan([inst], store_all=True)
+        plan.solve()
+        g = plan.adjoint()
+        torch.cuda.synchronize()
+        J = plan.values(0).cpu().numpy().astype(np.float64)
+        pi = plan.policy(0).cpu().numpy()
+        u0 = int(plan.u0.cpu()[0])
+        go = oracle.adjoint(inst, J, pi, u0)["grad"]
+        gt = oracle.tangent(inst, J, pi, u0)
+        np.testing.assert_allclose(g.cpu().numpy()[0], go, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(go, gt, rtol=1e-9, atol=1e-12)
+
+
+def test_autograd_function(torch):
+    from paper_2104_01284_amd.autograd import EcoDPValue
+    inst = ins.plain()
+    say("autograd EcoDPValue")
+    theta = torch.tensor(inst["theta"], dtype=torch.float64, requires_grad=True)
+    V = EcoDPValue.apply(theta, inst)
+    V.backward()
+    r = oracle.solve(inst)
+    assert abs(V.item() - r["V0"]) <= 1e-4 * abs(r["V0"])
+    plan = Plan([inst], store_all=True)
+    plan.solve()
+    g = plan.adjoint()[0].cpu().numpy()
+    np.testing.assert_allclose(theta.grad.numpy(), g, rtol=1e-12)
+    # against the FP64 tangent of the oracle's own solve (policy may differ at near-ties)
+    gt = oracle.tangent(inst, r["J"], r["pi"], r["u0"])
+    np.testing.assert_allclose(theta.grad.numpy(), gt, rtol=2e-3)
+
+
+def test_multi_instance_plan_equals_single(torch):
+    insts = [ins.plain()] + ragged_instances()
+    say("multi-instance plan of", len(insts))
+    big = Plan(insts, store_all=True)
+    V0b, u0b = big.solve()
+    torch.cuda.synchronize()
+    for b, inst in enumerate(insts):
+        one = Plan([inst], store_all=True)
+        V0, u0 = one.solve()
+        torch.cuda.synchronize()
+        assert float(V0b[b]) == float(V0[0]) and int(u0b[b]) == int(u0[0])
+        assert torch.equal(big.values(b), one.values(0))
+        assert torch.equal(big.policy(b), one.policy(0))
+
+
+def test_realistic_against_golden(torch):
+    path = os.path.join(GOLDEN, "realistic_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    with open(path) as f:
+        g = json.load(f)
+    inst = ins.realistic()
+    say("realistic_2km full solve")
+    plan = Plan([inst], store_all=True)
+    V0, u0 = plan.solve()
+    torch.cuda.synchronize()
+    Vg = float(V0.cpu()[0])
+    say("V0 gpu", Vg, "oracle", g["V0"], "rel", abs(Vg - g["V0"]) / abs(g["V0"]))
+    assert abs(Vg - g["V0"]) <= 1e-4 * abs(g["V0"])
+    J = plan.values(0)
+    s = np.array(g["samples"])
+    k, i, j, m = (s[:, q].astype(int) for q in range(4))
+    idx = [torch.as_tensor(x, device=J.device) for x in (k, i, j, m)]
+    Jg = J[idx[0], idx[1], idx[2], idx[3]].cpu().numpy().astype(np.float64)
+    err = np.abs(Jg - s[:, 4]) / np.maximum(1.0, np.abs(s[:, 4]))
+    say("sampled end-to-end J max rel error", float(err.max()))
+    assert err.max() < 1e-4
+
+
+def test_realistic_sampled_isolated_stages(torch):
+    """Full-size launch configuration: the GPU's own J_{k+1} fed to both the
+    GPU step and the oracle, compared on sampled nodes."""
+    inst = ins.realistic()
+    plan = Plan([inst], store_all=True)
+    plan.solve()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    I = oracle.Instance(inst)
+    for k in (0, 42, 43, 120, 199):
+        say("realistic_2km sampled stage", k)
+        Jn = plan.values(0)[k + 1].cpu().numpy()
+        Jg = plan.values(0)[k].cpu().numpy().astype(np.float64)
+        pg = plan.policy(0, k).cpu().numpy()
+        Jn64 = Jn.astype(np.float64).ravel()
+        for _ in range(200):
+            i, j, m = int(rng.integers(0, 101)), int(rng.integers(0, 41)), int(rng.integers(0, 201))
+            Jo, po, q2 = oracle.node(I, k, Jn64, i, j, m)
+            assert abs(Jg[i, j, m] - Jo) <= REL_J * max(1.0, abs(Jo)), (k, i, j, m, Jg[i, j, m], Jo)
+            if pg[i, j, m] != po:
+                assert q2 - Jo < REL_GAP * max(1.0, abs(Jo)), (k, i, j, m, pg[i, j, m], po, q2 - Jo)

@@ -571,3 +571,16 @@ def test_fuel_map_monomials():
         st, o = oracle.transition(x, 0, v, 0.5, 1, 1)
         assert o["mf"] == pytest.approx(mono[q], rel=1e-15)
         assert o["cost"] == pytest.approx((mono[q] + x["theta"][3]) * o["dt"], rel=1e-14)
+
+
+def test_single_node_matches_stage_sweep():
+    """The per-node evaluation used for sampled checks at full size is the
+    same rule as the stage sweep (including signal, WAIT and speed limit)."""
+    inst = ins.plain()
+    r = oracle.solve(inst, q2=True)
+    rng = np.random.default_rng(7)
+    for k in (0, 29, 30, 31, 49):
+        for _ in range(40):
+            i, j, m = (int(rng.integers(0, n)) for n in (21, 11, 31))
+            J, pi, q2 = oracle.node(inst, k, r["J"][k + 1], i, j, m)
+            assert J == r["J"][k, i, j, m] and pi == r["pi"][k, i, j, m] and q2 == r["q2"][k, i, j, m]
