@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--workload", default="realistic", choices=sorted(DESCR))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
@@ -76,6 +78,18 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_MiB": args.copy_calibration, "copies": 3,
+                          "expected_fetch_KiB_per_copy": args.copy_calibration * 1024,
+                          "expected_write_KiB_per_copy": args.copy_calibration * 1024}))
+        return
     inst = instances.make(args.workload)
     print(f"[bench] workload {DESCR[args.workload]}", file=sys.stderr, flush=True)
     plan = Plan([inst], store_all=True, timing=True)

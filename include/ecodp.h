@@ -90,7 +90,8 @@ typedef struct {
 typedef struct {
     uint32_t flags;            /* DP_STORE_ALL_V | DP_TIMING                                       */
     int32_t kernel;            /* 0 = automatic choice of the state-sweep variant                  */
-    int32_t tile[4];           /* 0 = automatic; tile[0] = SoC rows per workgroup                  */
+    int32_t tile[4];           /* 0 = automatic; tile[0] = SoC rows per workgroup (4, 8, 16),
+                                  tile[1] = workgroups sharing one node tile (control slices, <= 16) */
 } dp_options;
 
 typedef struct dp_plan dp_plan;

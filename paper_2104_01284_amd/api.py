@@ -70,7 +70,7 @@ class Plan:
     """
 
     def __init__(self, instances, store_all: bool = False, timing: bool = False, device: int = 0,
-                 sweep_tile: int = 0):
+                 sweep_tile: int = 0, kernel: int = 0, split: int = 0):
         import torch
         self.torch = torch
         if isinstance(instances, dict):
@@ -82,6 +82,8 @@ class Plan:
         opt = L.DpOptions()
         opt.flags = (L.DP_STORE_ALL_V if store_all else 0) | (L.DP_TIMING if timing else 0)
         opt.tile[0] = int(sweep_tile)
+        opt.tile[1] = int(split)
+        opt.kernel = int(kernel)   # 0 automatic, 1 simple per-node sweep, 2 grouped LDS sweep
         self.store_all = store_all
         self.device = device
         h = C.c_void_p()

@@ -1,6 +1,7 @@
 // Host side of the ecodp C ABI: validation, FP64 host preprocessing (grade
 // trigonometry, speed limits, signal red masks and wait times, Eq. 5c / 8),
 // buffer layout, and the enqueueing of the kernels on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -43,7 +44,13 @@ struct Inst {
     size_t S = 0;              // slab elements
     std::vector<int> light_of_stage;
     size_t J_off = 0, pi_off = 0, traj_off = 0;
-    size_t scr_st = 0, scr_bat = 0, scr_rho = 0;
+    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_batj = 0, scr_hdr = 0;
+    int sweep = 0;             // 1 = simple per-node kernel, 2 = grouped LDS kernel
+    int jt = 8;                // SoC rows per workgroup of the grouped kernel
+    int nsplit = 1;            // workgroups sharing one (speed node, SoC tile), each a slice of the controls
+    size_t scr_pv = 0, scr_pu = 0, scr_rec = 0, scr_q = 0;
+    int grid = 0;              // persistent workgroups of the grouped sweep
+    int H = 0;                 // bound on the SoC-cell shift of one step
     size_t tl_dev_off = 0;     // offset (entries) of this instance's TL table in the plan's TL array
     int64_t evals = 0;
 };
@@ -52,6 +59,7 @@ struct Inst {
 
 struct dp_plan {
     int device = 0;
+    int n_cu = 256, lds_per_cu = 160 * 1024;
     uint32_t flags = 0;
     dp_options opt{};
     std::vector<Inst> inst;
@@ -159,6 +167,41 @@ void build_tl(const dp_problem_desc &d, int L, TLEntry *out)
     }
 }
 
+// Bound on |r_xi' - j| over every node and control of every stage.  For a
+// speed node and a motor torque the battery current does not depend on the
+// engine torque; the step time is longest for the lowest engine torque on the
+// steepest uphill grade (least tractive force, most road load), and the
+// current is largest in magnitude at the lowest open-circuit voltage.
+int soc_shift_bound(const DevInst &P, const dp_problem_desc &d)
+{
+    double gmax = -1.0e300;
+    for (int k = 0; k < d.n_stages; k++) gmax = std::max(gmax, d.grade[k]);
+    const double cosa = 1.0 / std::sqrt(1.0 + gmax * gmax), sina = gmax * cosa;
+    const double xis[2] = {d.soc_lo, d.soc_hi};
+    double smax = 0.0;
+    for (int i = 1; i < P.n_v; i++) {
+        const double v = P.v_lo + i * P.hv;
+        if (!(v > 0.0)) continue;
+        for (int b = 0; b < P.n_m; b++) {
+            const double Tm = P.m_lo + b * P.hm;
+            const double Ftr = P.eta * (P.e_lo + Tm) * P.ig / P.rw;
+            const double Froad = P.M * P.g * (P.Crr * cosa + sina) + 0.5 * P.rho * P.CdA * v * v;
+            const double q = v * v + 2.0 * P.ds * (Ftr - Froad) / P.M;
+            const double v1 = q > 0.0 ? std::sqrt(q) : 0.0;
+            const double dt = 2.0 * P.ds / (v + v1);
+            const double Pm = Tm * v * P.ig / P.rw;
+            const double Pb = Pm >= 0.0 ? Pm / P.etam : Pm * P.etam;
+            for (double xi : xis) {
+                double I;
+                if (!battery_current(P, Pb, xi, I)) continue;
+                smax = std::max(smax, dt * std::fabs(I) / (P.Cnom * P.hs));
+            }
+        }
+    }
+    if (smax > 1.0e6) smax = 1.0e6;
+    return (int)std::ceil(smax) + 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -203,6 +246,13 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
     dp_plan *p = new (std::nothrow) dp_plan;
     if (!p) return fail(DP_ENOMEM, "host allocation");
     p->device = device;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+            p->lds_per_cu = prop.sharedMemPerBlock > 0 ? (int)prop.sharedMemPerBlock : 64 * 1024;
+        }
+    }
     if (opt) p->opt = *opt;
     p->flags = p->opt.flags;
     p->inst.resize(n_inst);
@@ -334,10 +384,89 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         pi_off += align_up(sizeof(int16_t) * I.S * N, 256);
         I.traj_off = traj_off;
         traj_off += (size_t)(N + 1) * 8;
+        // state-sweep variant: the grouped LDS kernel when its tables and
+        // staged planes fit, else the simple per-node kernel
+        I.H = soc_shift_bound(P, d);
+        // SoC rows per workgroup: the largest tile that still leaves about
+        // three resident waves per SIMD (LDS of one CU is shared by its
+        // workgroups); a caller tile overrides
+        const size_t lds_cu = (size_t)p->lds_per_cu;
+        const int waves = (d.n_t + 62) / 63;
+        auto waves_per_simd = [&](int t) {
+            const size_t bytes = lds_sweep_bytes(t, I.H, d.n_t);
+            if (bytes > lds_cu) return 0.0;
+            size_t wg = lds_cu / bytes;
+            if (wg * waves > 32) wg = 32 / waves;
+            return (double)(wg * waves) / 4.0;
+        };
+        int jt = 0;
+        if (p->opt.tile[0] == 4 || p->opt.tile[0] == 8 || p->opt.tile[0] == 16) {
+            jt = p->opt.tile[0];
+        } else {
+            const int cand[3] = {16, 8, 4};
+            double best_w = 0.0;
+            for (int t : cand) {
+                if (t > 4 && d.n_soc < t) continue;
+                const double w = waves_per_simd(t);
+                if (w >= 2.75) {
+                    jt = t;
+                    break;
+                }
+                if (w > best_w) {
+                    best_w = w;
+                    jt = t;
+                }
+            }
+            if (jt == 0) jt = 4;
+        }
+        const bool lds_fits = lds_sweep_bytes(jt, I.H, d.n_t) <= lds_cu && d.n_t <= 1008 && P.n_u <= 1024 &&
+                              d.n_v - 1 <= kSortBins;
+        I.jt = jt;
+        I.sweep = p->opt.kernel == 1 ? 1 : (lds_fits ? 2 : 1);
+        if (p->opt.kernel == 2 && !lds_fits) {
+            (void)hipFree(p->dev_params);
+            delete p;
+            return fail(DP_EUNSUPPORTED, "instance %d: grouped sweep does not fit (n_t %d, n_u %d, H %d)", b, d.n_t,
+                        P.n_u, I.H);
+        }
+        if (lds_fits) {
+            size_t wg = lds_cu / lds_sweep_bytes(jt, I.H, d.n_t);
+            if (wg * waves > 32) wg = 32 / waves;
+            if (wg < 1) wg = 1;
+            I.grid = (int)(wg * (size_t)p->n_cu);
+        }
         I.scr_st = scr;
-        scr += align_up(sizeof(StageEntry) * d.n_v * P.n_u, 256);
-        I.scr_bat = scr;
-        scr += align_up(sizeof(BatEntry) * (size_t)d.n_v * P.n_u * d.n_soc, 256);
+        scr += align_up(sizeof(SortedEntry) * d.n_v * P.n_u, 256);
+        I.scr_nf = scr;
+        scr += align_up(sizeof(int) * d.n_v, 256);
+        I.scr_bat = scr;   // BatEntry (simple kernel) or float2 weights (grouped kernel)
+        scr += align_up(sizeof(BatEntry) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
+        if (I.sweep == 2) {
+            const size_t ntiles = (d.n_soc + I.jt - 1) / I.jt;
+            // enough workgroups for 256 CUs: split the control list when the
+            // (speed node, SoC tile) grid alone is small
+            const long base_wg = (long)d.n_v * (long)ntiles;
+            int ns = (int)((2048 + base_wg - 1) / base_wg);
+            if (p->opt.tile[1] > 0) ns = p->opt.tile[1];
+            if (ns > 16) ns = 16;
+            if (ns > P.n_u) ns = P.n_u;
+            if (ns < 1) ns = 1;
+            I.nsplit = ns;
+            if (ns > 1) {
+                I.scr_pv = scr;
+                scr += align_up(sizeof(float) * I.S * ns, 256);
+                I.scr_pu = scr;
+                scr += align_up(sizeof(int16_t) * I.S * ns, 256);
+            }
+            I.scr_q = scr;
+            scr += align_up(sizeof(int) * 8 * (size_t)N, 256);
+            I.scr_rec = scr;
+            scr += align_up(sizeof(float) * (size_t)d.n_v * ntiles * P.n_u * (12 + 2 * I.jt), 256);
+            I.scr_batj = scr;
+            scr += align_up(sizeof(int) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
+            I.scr_hdr = scr;
+            scr += align_up(sizeof(int) * ((size_t)d.n_v * P.n_u * ntiles + 16), 256);
+        }
         I.scr_rho = scr;
         scr += align_up(sizeof(double) * I.S * 2, 256);
         I.evals = (int64_t)N * (int64_t)I.S * P.n_u;
@@ -388,13 +517,25 @@ static float *slab_ptr(dp_plan *p, const Inst &I, void *J, int k)
 }
 
 static int enqueue_stage(dp_plan *p, const Inst &I, int k, const float *Jn, float *Jk, int16_t *pik, void *scratch,
-                         hipStream_t s)
+                         hipStream_t s, bool zero_queue)
 {
     StageEntry *st = (StageEntry *)((char *)scratch + I.scr_st);
+    SortedEntry *sst = (SortedEntry *)((char *)scratch + I.scr_st);
+    int *nfeas = (int *)((char *)scratch + I.scr_nf);
     BatEntry *bat = (BatEntry *)((char *)scratch + I.scr_bat);
     const int L = I.light_of_stage[k];
     const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
-    if (launch_stage_table(I.P, k, st, bat, s)) return hip_fail(hipGetLastError(), "stage table launch");
+    float2 *batw = (float2 *)((char *)scratch + I.scr_bat);
+    int *batj = (int *)((char *)scratch + I.scr_batj);
+    int *hdr = (int *)((char *)scratch + I.scr_hdr);
+    if (I.sweep == 2) {
+        if (zero_queue && launch_fill_i32((int *)((char *)scratch + I.scr_q) + 8 * k, 8, 0, s))
+            return hip_fail(hipGetLastError(), "queue reset launch");
+        if (launch_stage_sorted(I.P, k, I.jt, sst, nfeas, batw, batj, hdr, (float *)((char *)scratch + I.scr_rec), s))
+            return hip_fail(hipGetLastError(), "stage table launch");
+    } else {
+        if (launch_stage_table(I.P, k, st, bat, s)) return hip_fail(hipGetLastError(), "stage table launch");
+    }
     const bool timing = (p->flags & DP_TIMING) != 0;
     if (timing) {
         if (p->n_ev_used + 2 > (int)p->ev.size()) {
@@ -406,7 +547,14 @@ static int enqueue_stage(dp_plan *p, const Inst &I, int k, const float *Jn, floa
         }
         (void)hipEventRecord(p->ev[p->n_ev_used], s);
     }
-    if (launch_sweep(I.P, k, Jn, Jk, pik, st, bat, tl, s)) return hip_fail(hipGetLastError(), "sweep launch");
+    float *part_v = (float *)((char *)scratch + I.scr_pv);
+    int16_t *part_u = (int16_t *)((char *)scratch + I.scr_pu);
+    int *queue = (int *)((char *)scratch + I.scr_q) + 8 * k;
+    const int rc = I.sweep == 2 ? launch_sweep_lds(I.jt, I.P, k, Jn, Jk, pik, nfeas,
+                                                   (const float *)((char *)scratch + I.scr_rec), batj, tl, I.H,
+                                                   I.nsplit, part_v, part_u, queue, I.grid, s)
+                                : launch_sweep(I.P, k, Jn, Jk, pik, st, bat, tl, s);
+    if (rc) return hip_fail(hipGetLastError(), "sweep launch");
     if (timing) {
         (void)hipEventRecord(p->ev[p->n_ev_used + 1], s);
         p->n_ev_used += 2;
@@ -424,9 +572,11 @@ int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_
     for (size_t b = 0; b < p->inst.size(); b++) {
         const Inst &I = p->inst[b];
         if (launch_terminal(I.P, slab_ptr(p, I, J, I.N), s)) return hip_fail(hipGetLastError(), "terminal launch");
+        if (I.sweep == 2 && launch_fill_i32((int *)((char *)scratch + I.scr_q), 8L * I.N, 0, s))
+            return hip_fail(hipGetLastError(), "queue reset launch");
         for (int k = I.N - 1; k >= 0; k--) {
             int16_t *pik = (int16_t *)((char *)pi + I.pi_off) + (size_t)k * I.S;
-            int rc = enqueue_stage(p, I, k, slab_ptr(p, I, J, k + 1), slab_ptr(p, I, J, k), pik, scratch, s);
+            int rc = enqueue_stage(p, I, k, slab_ptr(p, I, J, k + 1), slab_ptr(p, I, J, k), pik, scratch, s, false);
             if (rc) return rc;
         }
         if (launch_root(I.P, slab_ptr(p, I, J, 1), V0_dev + b, u0_dev + b, s))
@@ -447,7 +597,7 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
     if (J_next == J_out) return fail(DP_EINVAL, "J_next and J_out must not alias");
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    return enqueue_stage(p, I, k, J_next, J_out, pi_out, scratch, (hipStream_t)stream);
+    return enqueue_stage(p, I, k, J_next, J_out, pi_out, scratch, (hipStream_t)stream, true);
 }
 
 int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_dev, int32_t *status_dev, void *stream)

@@ -12,6 +12,7 @@ namespace ecodp {
 // rounding; nodes above the stage-N speed limit take J_inf.
 __global__ void k_terminal(DevInst P, float *__restrict__ JN)
 {
+#pragma clang fp contract(off)
     const long S = (long)P.n_v * P.n_s * P.n_t;
     for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
         const int m = (int)(n % P.n_t);
@@ -122,7 +123,11 @@ __global__ void __launch_bounds__(1024) k_sweep_naive(DevInst P, int k, const fl
         best[q] = Jinf;
         bu[q] = -1;
     }
-    const double v = P.v_lo + i * P.hv;
+    double v;
+    {
+#pragma clang fp contract(off)
+        v = P.v_lo + i * P.hv;
+    }
     const bool row_ok = !(v > P.vmax[k]);
     if (row_ok) {
         const StageEntry *sti = st + (long)i * P.n_u;

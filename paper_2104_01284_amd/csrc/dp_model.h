@@ -8,6 +8,8 @@
 
 namespace ecodp {
 
+constexpr int kSortBins = 4096;   // speed-cell bins of the per-node control sort
+
 // Per-instance constants, passed to kernels by value.
 struct DevInst {
     int N, n_v, n_s, n_t, n_e, n_m, n_u;
@@ -38,10 +40,29 @@ struct StageEntry {
     int16_t dtc;   // whole time cells advanced
 };
 
+// Stage data of one (speed node, control) in the order the grouped sweep
+// visits it: ascending next-stage speed cell, ascending control inside a cell.
+struct SortedEntry {
+    float c;
+    float fv, gv;
+    float ft, gt;
+    int32_t iv;    // lower speed cell of the successor (>= 0: infeasible pairs are dropped)
+    int32_t dtc;   // whole time cells advanced
+    int32_t u;     // control index a * n_m + b
+};
+
 // Per-(speed node, control, SoC node) battery coordinate.
 struct BatEntry {
     int32_t jx;    // lower SoC cell in [0, n_s - 2]; -1 = infeasible
     float fx, gx;
+};
+
+// Scalars the grouped sweep needs (kept small: everything here lives in SGPRs).
+struct SweepArgs {
+    int n_v, n_t, n_s, n_u, zero_row, wait;
+    float Jinf;
+    double v_lo, hv;
+    const double *vmax;
 };
 
 // Per-(signal, time node) data, host FP64.

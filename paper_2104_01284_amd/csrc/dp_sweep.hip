@@ -1,0 +1,581 @@
+// Grouped, LDS-staged state sweep (Sec. IV "Kernel 2") for gfx950.
+//
+// For a fixed output speed node i and control u every interpolation weight
+// and every cell offset is the same for all time nodes (the time coordinate
+// advances by the same dt/h_t from every node) and the same for all time
+// nodes of one SoC node.  The sweep therefore runs lanes over time nodes with
+// a wave-uniform control loop, and
+//  * visits the controls of node i grouped by their successor's lower speed
+//    cell iv (ascending, controls ascending inside a group), so the two
+//    next-stage speed planes iv, iv+1 (the SoC rows of the tile plus a halo,
+//    all times) are staged into LDS once per group;
+//  * interpolates in speed first (V), then in time with the neighbouring
+//    lane's V obtained by a DPP wave shift (one LDS read per plane and time),
+//    and shares each (speed, time) bilinear row T between the two SoC nodes
+//    whose SoC cell it bounds;
+//  * keeps the running minimum and argmin of a tile of SoC nodes in registers.
+// A wave covers 63 consecutive time nodes; its lane 63 only supplies the time
+// neighbour of lane 62.  Exact FP32 ties keep the first control visited.
+#include "dp_internal.h"
+
+namespace ecodp {
+
+// ------------------------------------------------------- sorted stage table --
+
+// One workgroup per speed node i, one thread per control: the FP64 powertrain
+// model (as the per-pair stage table) and a stable counting sort of the
+// feasible controls by successor speed cell.
+__global__ void __launch_bounds__(1024) k_stage_sort(DevInst P, int k, SortedEntry *__restrict__ out,
+                                                     int *__restrict__ nfeas)
+{
+    __shared__ int s_hist[kSortBins];
+    __shared__ int s_min, s_max, s_cnt;
+    const int i = blockIdx.x;
+    const int u = threadIdx.x;
+    const int nu = P.n_u;
+    if (u == 0) {
+        s_min = 0x7fffffff;
+        s_max = -1;
+        s_cnt = 0;
+    }
+    for (int q = threadIdx.x; q < kSortBins; q += blockDim.x) s_hist[q] = 0;
+    __syncthreads();
+    SortedEntry e;
+    int iv = -1;
+    if (u < nu) {
+#pragma clang fp contract(off)
+        const double v = P.v_lo + i * P.hv;
+        const PT p = powertrain(P, k, v, u / P.n_m, u % P.n_m);
+        bool ok = p.st == 0;
+        int c = 0, dtc = 0;
+        double fv = 0.0, ft = 0.0;
+        if (ok) {
+            const double rv = (p.v1 - P.v_lo) / P.hv;
+            if (!(rv >= 0.0 && rv <= P.n_v - 1)) ok = false;
+            else cell_of(rv, P.n_v, c, fv);
+            const double delta = p.dt / P.ht;
+            if (!(delta < P.n_t)) {
+                ok = false;
+            } else {
+                const double fl = floor(delta);
+                dtc = (int)fl;
+                ft = delta - fl;
+            }
+        }
+        e.c = (float)p.cost;
+        e.fv = (float)fv;
+        e.gv = (float)(1.0 - fv);
+        e.ft = (float)ft;
+        e.gt = (float)(1.0 - ft);
+        e.iv = c;
+        e.dtc = dtc;
+        e.u = u;
+        if (ok) iv = c;
+    }
+    if (iv >= 0) {
+        atomicMin(&s_min, iv);
+        atomicMax(&s_max, iv);
+        atomicAdd(&s_cnt, 1);
+    }
+    __syncthreads();
+    if (s_cnt == 0) {
+        if (threadIdx.x == 0) nfeas[i] = 0;
+        return;
+    }
+    const int base = s_min;
+    if (iv >= 0) atomicAdd(&s_hist[iv - base], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        const int bins = s_max - s_min + 1;
+        for (int q = 0; q < bins; q++) {
+            const int c = s_hist[q];
+            s_hist[q] = run;
+            run += c;
+        }
+        nfeas[i] = s_cnt;
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int ww = 0; ww < nw; ww++) {
+        if (w == ww) {
+            const unsigned long long active = __ballot(iv >= 0);
+            unsigned long long rem = active;
+            int rank = 0, cnt = 0;
+            while (rem) {
+                const int leader = __ffsll((long long)rem) - 1;
+                const int val = __builtin_amdgcn_readlane(iv, leader);
+                const unsigned long long msk = __ballot(iv == val) & active;
+                if (iv == val) {
+                    rank = __popcll(msk & __lanemask_lt());
+                    cnt = __popcll(msk);
+                }
+                rem &= ~msk;
+            }
+            if (iv >= 0) {
+                const int pos = s_hist[iv - base] + rank;
+                out[(long)i * nu + pos] = e;
+                if (rank == cnt - 1) s_hist[iv - base] += cnt;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Dwords of one packed record: the sorted entry (c, fv, gv, ft, gt, iv, dtc,
+// u), the tile header, padding, then the tile's (fx, gx) pairs.
+__host__ __device__ constexpr int rec_words(int JT) { return 12 + 2 * JT; }
+
+// Battery coordinates of one (speed node, sorted position, SoC tile), written
+// as one packed record per (speed node, tile, position) so that the sweep
+// stages a run of controls with one contiguous copy: per SoC node the lower
+// cell (also kept in batj for the general path) and the weights (fx, gx);
+// the header is the first node's cell when the tile's cells are consecutive
+// (jx0 + q), else -1.
+__global__ void k_stage_bat_sorted(DevInst P, int k, int JT, int ntiles, const SortedEntry *__restrict__ st,
+                                   const int *__restrict__ nfeas, int *__restrict__ batj, float *__restrict__ rec)
+{
+#pragma clang fp contract(off)
+    const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long total = (long)P.n_v * P.n_u * ntiles;
+    if (idx >= total) return;
+    const int tile = (int)(idx % ntiles);
+    const long ir = idx / ntiles;
+    const int r = (int)(ir % P.n_u);
+    const int i = (int)(ir / P.n_u);
+    if (r >= nfeas[i]) return;
+    const SortedEntry e = st[ir];
+    const int u = e.u;
+    const double v = P.v_lo + i * P.hv;
+    const PT p = powertrain(P, k, v, u / P.n_m, u % P.n_m);
+    const int j0 = tile * JT;
+    const int jc = min(JT, P.n_s - j0);
+    const int CW = rec_words(JT);
+    float *out = rec + (((long)i * ntiles + tile) * P.n_u + r) * CW;
+    int jx0 = -1;
+    bool regular = true;
+    for (int q = 0; q < JT; q++) {
+        int jx = -1;
+        double fx = 0.0;
+        if (q < jc) {
+            const int j = j0 + q;
+            double I;
+            const double xi = P.s_lo + j * P.hs;
+            if (battery_current(P, p.Pb, xi, I)) {
+                const double rs = (double)j - (p.dt * I) / (P.Cnom * P.hs);
+                if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
+            }
+            batj[ir * P.n_s + j] = jx;
+            if (q == 0) jx0 = jx;
+            regular = regular && jx >= 0 && jx == jx0 + q;
+        }
+        out[12 + 2 * q] = jx >= 0 ? (float)fx : 0.0f;
+        out[13 + 2 * q] = jx >= 0 ? (float)(1.0 - fx) : 0.0f;
+    }
+    const float *ef = reinterpret_cast<const float *>(&e);
+    for (int w = 0; w < 8; w++) out[w] = ef[w];
+    out[8] = __int_as_float(regular ? jx0 : -1);
+    out[9] = out[10] = out[11] = 0.0f;
+}
+
+// ------------------------------------------------------------------ sweep --
+
+__device__ inline float shl1(float x)
+{
+    // lane l receives lane l+1 (wave-wide shift); lane 63 receives 0
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, true));
+}
+
+// Registers per thread that prefetch the next run of control records.
+constexpr int kPrefetch = 4;
+
+template <int JT, int PITCH>
+__global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const float *__restrict__ Jn,
+                                                    float *__restrict__ Jk, int16_t *__restrict__ pik,
+                                                    const int *__restrict__ nfeas, const float *__restrict__ rec,
+                                                    const int *__restrict__ batj, const TLEntry *__restrict__ tl,
+                                                    int H, int ntiles, int rw, int nsplit, float *__restrict__ part_v,
+                                                    int16_t *__restrict__ part_u, int *__restrict__ queue)
+{
+    extern __shared__ float lds[];
+    constexpr int CW = rec_words(JT);
+    const int nt = P.n_t, ns = P.n_s, nu = P.n_u;
+    // Persistent workgroups take (speed node, SoC tile, control slice) items
+    // from eight queues, one contiguous band of speed nodes per XCD (blocks
+    // are dealt round-robin over the 8 XCDs, so a band stays in one L2); a
+    // workgroup whose band is drained takes items from the other bands.
+    // Every workgroup exits once all queues are drained.
+    __shared__ int s_item;
+    const int nitems = P.n_v * ntiles * nsplit;
+    const int home = blockIdx.x & 7;
+    int qi = 0;
+    for (;;) {
+    if (threadIdx.x == 0) {
+        int item = -1;
+        while (qi < 8) {
+            const int x = (home + qi) & 7;
+            const int lo = (int)(((long)nitems * x) >> 3), hi = (int)(((long)nitems * (x + 1)) >> 3);
+            const int got = lo + atomicAdd(&queue[x], 1);
+            if (got < hi) {
+                item = got;
+                break;
+            }
+            qi++;
+        }
+        s_item = item;
+    }
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item < 0) break;
+    const int i = item / (ntiles * nsplit);
+    const int rem = item - i * ntiles * nsplit;
+    const int tile = rem / nsplit;
+    const int split = rem - tile * nsplit;
+    const int j0 = tile * JT;
+    const int jc = min(JT, ns - j0);
+    const int wlo = max(0, j0 - H);
+    const int whi = min(ns - 1, j0 + jc + H);
+    const int nrows = whi - wlo + 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = wave * 63 + lane;
+    const bool out_lane = lane < 63 && m < nt;
+    const float Jinf = P.Jinf;
+    float best[JT];
+    int bu[JT];
+#pragma unroll
+    for (int q = 0; q < JT; q++) {
+        best[q] = Jinf;
+        bu[q] = -1;
+    }
+    double v;
+    {
+#pragma clang fp contract(off)
+        v = P.v_lo + i * P.hv;
+    }
+    const bool row_ok = !(v > P.vmax[k]);
+    const int nf = row_ok ? nfeas[i] : 0;
+    const int r_begin = (int)(((long)nf * split) / nsplit);
+    const int r_end = (int)(((long)nf * (split + 1)) / nsplit);
+    const long SV = (long)ns * nt;
+    const int slot_sz = rw * PITCH;              // floats per staged plane
+    float *chunk = lds + 2 * slot_sz;             // kPrefetch * blockDim floats
+    const int cc = (kPrefetch * (int)blockDim.x) / CW;   // controls per staged run
+    const float *recs = rec + ((long)i * ntiles + tile) * nu * CW;
+    int plane[2] = {-1, -1};
+    int cur_p = -2;
+    int SA = 0, SB = 0;   // LDS float offsets of the staged planes cur_p, cur_p + 1
+
+    float pre[kPrefetch];
+    auto fetch = [&](int c0) {
+        const int cnw = min(cc, r_end - c0) * CW;
+        const float *src = recs + (long)c0 * CW;
+#pragma unroll
+        for (int q = 0; q < kPrefetch; q++) {
+            const int x = threadIdx.x + q * blockDim.x;
+            pre[q] = x < cnw ? src[x] : 0.0f;
+        }
+    };
+
+    if (r_begin < r_end) fetch(r_begin);
+    for (int c0 = r_begin; c0 < r_end; c0 += cc) {
+        __syncthreads();                           // the previous run is no longer read
+#pragma unroll
+        for (int q = 0; q < kPrefetch; q++) chunk[threadIdx.x + q * blockDim.x] = pre[q];
+        __syncthreads();
+        if (c0 + cc < r_end) fetch(c0 + cc);        // in flight while this run is processed
+        const int cn = min(cc, r_end - c0);
+        for (int cr = 0; cr < cn; cr++) {
+            const float *ce = chunk + cr * CW;
+            const int p = __builtin_amdgcn_readfirstlane(__float_as_int(ce[5]));
+            if (p != cur_p) {
+                // stage planes p and p+1 (SoC rows wlo..whi, every time node),
+                // keeping a plane already resident from the previous group
+                int sp = plane[0] == p ? 0 : (plane[1] == p ? 1 : -1);
+                int sq = plane[0] == p + 1 ? 0 : (plane[1] == p + 1 ? 1 : -1);
+                const bool need_p = sp < 0, need_q = sq < 0;
+                if (need_p && need_q) {
+                    sp = 0;
+                    sq = 1;
+                } else if (need_p) {
+                    sp = 1 - sq;
+                } else if (need_q) {
+                    sq = 1 - sp;
+                }
+                __syncthreads();
+                for (int rr = 0; rr < nrows; rr++)
+                    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+                        const long g = (long)(wlo + rr) * nt + t;
+                        if (need_p) lds[sp * slot_sz + rr * PITCH + t] = Jn[(long)p * SV + g];
+                        if (need_q) lds[sq * slot_sz + rr * PITCH + t] = Jn[(long)(p + 1) * SV + g];
+                    }
+                plane[sp] = p;
+                plane[sq] = p + 1;
+                SA = sp * slot_sz;
+                SB = sq * slot_sz;
+                cur_p = p;
+                __syncthreads();
+            }
+            const float c0f = ce[0], fv = ce[1], gv = ce[2], ft = ce[3], gt = ce[4];
+            const int dtc = __float_as_int(ce[6]);
+            const int u = __float_as_int(ce[7]);
+            const int jx0 = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
+            const int pos = m + dtc;
+            const bool okt = out_lane && (pos < nt - 1 || (pos == nt - 1 && ft == 0.0f));
+            const int posc = min(pos, nt - 1);
+            // lanes whose successor time is off the grid get an infinite stage
+            // cost, so their candidates never win
+            const float c = okt ? c0f : __builtin_inff();
+            const bool regular = jx0 >= wlo && jx0 + jc <= whi;
+            const float *wp = ce + 12;
+            float Qv[JT];
+            if (regular && jc == JT) {
+                const int a0 = SA + (jx0 - wlo) * PITCH + posc;
+                const int b0 = SB + (jx0 - wlo) * PITCH + posc;
+                // speed lerp on the JT+1 SoC rows, then the time lerp with the
+                // neighbouring lane, then the SoC lerp per node
+                float V[JT + 1];
+#pragma unroll
+                for (int q = 0; q <= JT; q++) V[q] = fmaf(fv, lds[b0 + q * PITCH], gv * lds[a0 + q * PITCH]);
+                float T[JT + 1];
+#pragma unroll
+                for (int q = 0; q <= JT; q++) T[q] = fmaf(gt, V[q], ft * shl1(V[q]));
+#pragma unroll
+                for (int q = 0; q < JT; q++) Qv[q] = fmaf(wp[2 * q], T[q + 1], fmaf(wp[2 * q + 1], T[q], c));
+            } else {
+                const int r = c0 + cr;
+#pragma unroll
+                for (int q = 0; q < JT; q++) {
+                    const int jx = q < jc ? batj[((long)i * nu + r) * ns + j0 + q] : -1;
+                    Qv[q] = Jinf;
+                    if (jx >= 0) {
+                        float V0, V1;
+                        if (jx >= wlo && jx + 1 <= whi) {
+                            const int a = SA + (jx - wlo) * PITCH + posc;
+                            const int b = SB + (jx - wlo) * PITCH + posc;
+                            V0 = fmaf(fv, lds[b], gv * lds[a]);
+                            V1 = fmaf(fv, lds[b + PITCH], gv * lds[a + PITCH]);
+                        } else {
+                            const float *a = Jn + (long)p * SV + (long)jx * nt + posc;
+                            V0 = fmaf(fv, a[SV], gv * a[0]);
+                            V1 = fmaf(fv, a[SV + nt], gv * a[nt]);
+                        }
+                        const float T0 = fmaf(gt, V0, ft * shl1(V0));
+                        const float T1 = fmaf(gt, V1, ft * shl1(V1));
+                        Qv[q] = fmaf(wp[2 * q], T1, fmaf(wp[2 * q + 1], T0, c));
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < JT; q++) {
+                const bool upd = Qv[q] < best[q];
+                best[q] = upd ? Qv[q] : best[q];
+                bu[q] = upd ? u : bu[q];
+            }
+        }
+    }
+    if (out_lane && nsplit > 1) {
+        // partial minimum of this control slice; the combine kernel finishes
+        const long plane_nodes = (long)P.n_v * SV;
+#pragma unroll
+        for (int q = 0; q < JT; q++) {
+            if (q < jc) {
+                const long n = ((long)i * ns + j0 + q) * nt + m;
+                part_v[split * plane_nodes + n] = best[q];
+                part_u[split * plane_nodes + n] = (int16_t)bu[q];
+            }
+        }
+    } else if (out_lane) {
+        TLEntry t;
+        const bool has_tl = tl != nullptr;
+        if (has_tl) t = tl[m];
+#pragma unroll
+        for (int q = 0; q < JT; q++) {
+            if (q < jc) {
+                const int j = j0 + q;
+                float J = best[q];
+                int pu = bu[q];
+                if (has_tl && t.red) {
+                    J = Jinf;
+                    pu = -1;
+                    if (i == P.zero_row && P.wait && t.wc >= 0) {
+                        const float *pw = Jn + ((long)i * ns + j) * nt + t.wc;
+                        const float w = t.wcost + (t.wg32 * pw[0] + t.wf32 * pw[1]);
+                        if (w < Jinf) {
+                            J = w;
+                            pu = -2;
+                        }
+                    }
+                }
+                const long n = ((long)i * ns + j) * nt + m;
+                Jk[n] = J;
+                pik[n] = (int16_t)pu;
+            }
+        }
+    }
+    }   // item loop
+}
+
+// Minimum over the control splits (the first split wins a tie, so the result
+// does not depend on the number of splits), then the signal override and the
+// store of J_k and pi_k.
+__global__ void k_sweep_combine(SweepArgs P, int nv, int nsplit, const float *__restrict__ part_v,
+                                const int16_t *__restrict__ part_u, const float *__restrict__ Jn,
+                                float *__restrict__ Jk, int16_t *__restrict__ pik, const TLEntry *__restrict__ tl)
+{
+    const long S = (long)nv * P.n_s * P.n_t;
+    for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
+        float J = part_v[n];
+        int pu = part_u[n];
+        for (int sp = 1; sp < nsplit; sp++) {
+            const float x = part_v[sp * S + n];
+            if (x < J) {
+                J = x;
+                pu = part_u[sp * S + n];
+            }
+        }
+        if (tl != nullptr) {
+            const int m = (int)(n % P.n_t);
+            const TLEntry t = tl[m];
+            if (t.red) {
+                const long ij = n / P.n_t;
+                const int i = (int)(ij / P.n_s);
+                J = P.Jinf;
+                pu = -1;
+                if (i == P.zero_row && P.wait && t.wc >= 0) {
+                    const float *pw = Jn + ij * P.n_t + t.wc;
+                    const float w = t.wcost + (t.wg32 * pw[0] + t.wf32 * pw[1]);
+                    if (w < P.Jinf) {
+                        J = w;
+                        pu = -2;
+                    }
+                }
+            }
+        }
+        Jk[n] = J;
+        pik[n] = (int16_t)pu;
+    }
+}
+
+// ----------------------------------------------------------------- launch --
+
+int launch_stage_sorted(const DevInst &P, int k, int JT, SortedEntry *st, int *nfeas, float2 *, int *batj, int *,
+                        float *rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage_sort, dim3(P.n_v), dim3(1024), 0, s, P, k, st, nfeas);
+    if (hipGetLastError() != hipSuccess) return -1;
+    const int ntiles = (P.n_s + JT - 1) / JT;
+    const long total = (long)P.n_v * P.n_u * ntiles;
+    hipLaunchKernelGGL(k_stage_bat_sorted, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P, k, JT, ntiles,
+                       st, nfeas, batj, rec);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+static SweepArgs sweep_args(const DevInst &P)
+{
+    SweepArgs a;
+    a.n_v = P.n_v;
+    a.n_t = P.n_t;
+    a.n_s = P.n_s;
+    a.n_u = P.n_u;
+    a.zero_row = P.zero_row;
+    a.wait = P.wait;
+    a.Jinf = (float)P.Jinf;
+    a.v_lo = P.v_lo;
+    a.hv = P.hv;
+    a.vmax = P.vmax;
+    return a;
+}
+
+size_t lds_sweep_bytes(int JT, int H, int n_t)
+{
+    const int pitch = ((n_t + 63) / 64) * 64;
+    const int threads = 64 * ((n_t + 62) / 63);
+    return sizeof(float) * (2 * (size_t)(JT + 2 * H + 2) * pitch + (size_t)kPrefetch * threads);
+}
+
+template <int JT, int PITCH>
+static int launch_lds_t(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const int *nfeas,
+                        const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit, float *part_v,
+                        int16_t *part_u, int *queue, int grid, hipStream_t s)
+{
+    const int ntiles = (P.n_s + JT - 1) / JT;
+    const int rw = JT + 2 * H + 2;
+    const int waves = (P.n_t + 62) / 63;
+    const size_t lds = lds_sweep_bytes(JT, H, P.n_t);
+    const int nitems = P.n_v * ntiles * nsplit;
+    hipLaunchKernelGGL((k_sweep_lds<JT, PITCH>), dim3(grid < nitems ? grid : nitems), dim3(64 * waves), lds, s,
+                       sweep_args(P), k, Jn, Jk, pik, nfeas, rec, batj, tl, H, ntiles, rw, nsplit, part_v, part_u,
+                       queue);
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (nsplit > 1) {
+        const long S = (long)P.n_v * P.n_s * P.n_t;
+        long blocks = (S + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL(k_sweep_combine, dim3((unsigned)blocks), dim3(256), 0, s, sweep_args(P), P.n_v, nsplit,
+                           part_v, part_u, Jn, Jk, pik, tl);
+        if (hipGetLastError() != hipSuccess) return -1;
+    }
+    return 0;
+}
+
+template <int JT>
+static int launch_lds_p(int pitch, const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik,
+                        const int *nfeas, const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit,
+                        float *part_v, int16_t *part_u, int *queue, int grid, hipStream_t s)
+{
+    switch (pitch) {
+#define ECODP_PITCH(X) \
+    case X: return launch_lds_t<JT, X>(P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue, grid, s);
+        ECODP_PITCH(64)
+        ECODP_PITCH(128)
+        ECODP_PITCH(192)
+        ECODP_PITCH(256)
+        ECODP_PITCH(320)
+        ECODP_PITCH(384)
+        ECODP_PITCH(448)
+        ECODP_PITCH(512)
+        ECODP_PITCH(576)
+        ECODP_PITCH(640)
+        ECODP_PITCH(704)
+        ECODP_PITCH(768)
+        ECODP_PITCH(832)
+        ECODP_PITCH(896)
+        ECODP_PITCH(960)
+        ECODP_PITCH(1024)
+#undef ECODP_PITCH
+    default: return -2;
+    }
+}
+
+int launch_sweep_lds(int JT, const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const int *nfeas,
+                     const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit, float *part_v,
+                     int16_t *part_u, int *queue, int grid, hipStream_t s)
+{
+    const int pitch = ((P.n_t + 63) / 64) * 64;
+    if (JT == 16)
+        return launch_lds_p<16>(pitch, P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue,
+                                grid, s);
+    if (JT == 8)
+        return launch_lds_p<8>(pitch, P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue,
+                               grid, s);
+    return launch_lds_p<4>(pitch, P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue, grid,
+                           s);
+}
+
+__global__ void k_fill_i32(int *p, long n, int v)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) p[q] = v;
+}
+
+int launch_fill_i32(int *p, long n, int v, hipStream_t s)
+{
+    long b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)b), dim3(256), 0, s, p, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ecodp

@@ -106,25 +106,27 @@ def test_plain_end_to_end(torch):
     say("end-to-end policy mismatches", mism, "outside the near-tie band", bad)
 
 
-def test_plain_stage_isolated_every_stage(torch):
+@pytest.mark.parametrize("kernel,tile", [(1, 0), (2, 4), (2, 8), (2, 16)])
+def test_plain_stage_isolated_every_stage(torch, kernel, tile):
     inst = ins.plain()
     r = oracle.solve(inst)
-    plan = Plan([inst])
+    plan = Plan([inst], kernel=kernel, sweep_tile=tile)
     tot = tot_abs = 0
     for k in range(inst["N"]):
-        say("plain_500m isolated stage", k)
+        say("plain_500m isolated stage", k, "kernel", kernel, "tile", tile)
         m, a = check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), "plain")
         tot += m
         tot_abs += a
     say("isolated mismatches (all in the near-tie band)", tot, "outside an absolute 1e-6 gap", tot_abs)
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("idx", range(5))
-def test_ragged_and_edge_instances(torch, idx):
+def test_ragged_and_edge_instances(torch, idx, kernel):
     inst = ragged_instances()[idx]
-    say("edge instance", idx, inst["name"], inst["v_grid"], inst["soc_grid"], inst["t_grid"])
+    say("edge instance", idx, inst["name"], inst["v_grid"], inst["soc_grid"], inst["t_grid"], "kernel", kernel)
     r = oracle.solve(inst, q2=True)
-    plan = Plan([inst], store_all=True)
+    plan = Plan([inst], store_all=True, kernel=kernel)
     V0, u0 = plan.solve()
     torch.cuda.synchronize()
     assert abs(float(V0.cpu()[0]) - r["V0"]) <= 1e-4 * abs(r["V0"])
