@@ -5,9 +5,11 @@ One step = one pass of the whole path over one synthetic problem: the
 backward recursion with stage tables, state sweeps, signal handling and the
 exact root step (dp_solve), the FP64 policy rollout (dp_rollout) and the
 fixed-policy adjoint (dp_adjoint).  Inputs are resident in HBM before the
-timed region.  Prints one JSON line.
+timed region.  Prints one JSON line.  The batched workload times the
+256-instance solve alone (one HIP-graph replay per step).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload realistic|large|plain|paper]
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+                  [--workload realistic|large|plain|paper|batched] [--kernel K] [--tile T] [--split S]
 """
 from __future__ import annotations
 
@@ -29,6 +31,8 @@ DESCR = {
     "large": "large_3km: 300 stages x 201x81x401 states x 41x21 controls, 8 signals, +-3% grade",
     "plain": "plain_500m: 50 stages x 21x11x31 states x 11x11 controls, 1 signal",
     "paper": "paper_shape: 20 stages x 35x26x40 states x 23x30 controls, 1 signal",
+    "batched": "batched_256: 256 heterogeneous solves, 50-200 stages, (41-101)x(21-41)x(61-201) states, "
+               "(21-41)x(11-21) controls, one HIP graph per solve",
 }
 
 
@@ -61,6 +65,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="realistic", choices=sorted(DESCR))
+    ap.add_argument("--tile", type=int, default=0, help="SoC rows per sweep workgroup (4, 8, 16; 0 automatic)")
+    ap.add_argument("--split", type=int, default=0, help="control slices per node tile (0 automatic)")
+    ap.add_argument("--wg-per-cu", type=int, default=0, help="resident sweep workgroups per CU (0 automatic)")
+    ap.add_argument("--kernel", type=int, default=0, help="sweep variant (0 automatic, 1 simple, 2 grouped)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's own sweep configuration instead of the autotuner's")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -90,22 +100,46 @@ def main():
                           "expected_fetch_KiB_per_copy": args.copy_calibration * 1024,
                           "expected_write_KiB_per_copy": args.copy_calibration * 1024}))
         return
-    inst = instances.make(args.workload)
+    batched = args.workload == "batched"
+    insts = instances.batched(256) if batched else [instances.make(args.workload)]
+    inst = insts[0]
     print(f"[bench] workload {DESCR[args.workload]}", file=sys.stderr, flush=True)
-    plan = Plan([inst], store_all=True, timing=True)
+    opts = dict(sweep_tile=args.tile, split=args.split, wg_per_cu=args.wg_per_cu, kernel=args.kernel)
+    tuned = None
+    if not args.no_tune and not (args.kernel or args.tile):
+        from paper_2104_01284_amd.autotune import tuned_options
+        t0 = time.perf_counter()
+        tuned = tuned_options(insts, verbose=True)
+        print(f"[bench] sweep autotune {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        opts["inst_opts"] = tuned
+    if batched:
+        # the batch is timed as recorded HIP-graph solves; the sweep launches
+        # are timed with events in a separate pass of an identical plan
+        plan = Plan(insts, store_all=False, graph=True, **opts)
+        tplan = Plan(insts, store_all=False, timing=True, **opts)
+        tplan.solve()
+        torch.cuda.synchronize()
+        tplan.sweep_time()
+        tplan.solve()
+        torch.cuda.synchronize()
+        sweep_ms, launches = tplan.sweep_time()
+        del tplan
+    else:
+        plan = Plan(insts, store_all=True, timing=True, **opts)
     evals = plan.evaluations()
     info = plan.info[0]
-    evals_per_stage = int(info.slab_elems) * int(info.n_u)
 
     def step():
         plan.solve()
-        plan.rollout()
-        plan.adjoint()
+        if not batched:
+            plan.rollout()
+            plan.adjoint()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.sweep_time()                       # discard warm-up sweep events
+    if not batched:
+        plan.sweep_time()                   # discard warm-up sweep events
 
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -115,17 +149,24 @@ def main():
         ev[q][0].record(stream)
         plan.solve()
         ev[q][1].record(stream)
-        plan.rollout()
-        plan.adjoint()
+        if not batched:
+            plan.rollout()
+            plan.adjoint()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sweep_ms, launches = plan.sweep_time()
+    if not batched:
+        sweep_ms, launches = plan.sweep_time()
+        sweep_ms /= args.steps
+        launches //= args.steps
     solve_ms = [a.elapsed_time(b) for a, b in ev]
     ms_per_step = wall * 1e3 / args.steps
     V0 = float(plan.V0.cpu()[0])
 
+    # sweep-kernel roofline over one solve: all state-control evaluations of
+    # the solve at the canonical FP32 work per evaluation, over the summed
+    # duration of its sweep launches
     avg_launch_ms = sweep_ms / max(1, launches)
-    achieved = FLOPS_PER_EVAL * evals_per_stage / (avg_launch_ms * 1e-3) / 1e12
+    achieved = FLOPS_PER_EVAL * evals / (sweep_ms * 1e-3) / 1e12
     out = {
         "metric": "state-control evals/s and full-horizon solve ms (FP32 vs FP64 oracle, 1e-4 rel V_0)",
         "value": evals / (ms_per_step * 1e-3),
@@ -135,16 +176,21 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": DESCR[args.workload], "evaluations_per_solve": evals,
-                   "step": "dp_solve + dp_rollout + dp_adjoint"},
+                   "step": "dp_solve (HIP graph)" if batched else "dp_solve + dp_rollout + dp_adjoint",
+                   "sweep": {"kernel": int(info.sweep_kernel),
+                             "tile": int(info.sweep_tile), "autotuned": tuned is not None,
+                             "split": int(info.sweep_split), "grid": int(info.sweep_grid),
+                             "soc_shift": int(info.soc_shift)}},
         "solve_ms": {"mean": statistics.mean(solve_ms),
                      "var": statistics.pvariance(solve_ms) if len(solve_ms) > 1 else 0.0,
                      "max": max(solve_ms), "median": statistics.median(solve_ms)},
         "solve_evals_per_s": evals / (statistics.mean(solve_ms) * 1e-3),
         "V0": V0,
+        "V0_all_mean": float(plan.V0.double().mean().cpu()) if batched else V0,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "state sweep", "avg_launch_ms": avg_launch_ms, "launches": launches,
-                     "flops_per_launch": FLOPS_PER_EVAL * evals_per_stage},
+                     "kernel": "state sweep", "avg_launch_ms": avg_launch_ms, "launches_per_solve": launches,
+                     "flops_per_launch": FLOPS_PER_EVAL * evals / max(1, launches)},
     }
     gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.json")
     if os.path.exists(gold):

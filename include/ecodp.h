@@ -60,6 +60,9 @@ enum {
 /* dp_options.flags */
 #define DP_STORE_ALL_V 1u      /* keep J_0..J_N (needed by dp_adjoint and for inspection) */
 #define DP_TIMING 2u           /* time every state-sweep launch with HIP events */
+#define DP_GRAPH 4u            /* dp_solve records its launches once into a HIP graph and replays it;
+                                  the graph is recorded again when the buffers change.  Not with
+                                  DP_TIMING. */
 
 /* One receding-horizon problem (Eq. 6-8).  Host pointers; copied at build. */
 typedef struct {
@@ -88,10 +91,14 @@ typedef struct {
 } dp_problem_desc;
 
 typedef struct {
-    uint32_t flags;            /* DP_STORE_ALL_V | DP_TIMING                                       */
-    int32_t kernel;            /* 0 = automatic choice of the state-sweep variant                  */
+    uint32_t flags;            /* DP_STORE_ALL_V | DP_TIMING | DP_GRAPH                            */
+    int32_t kernel;            /* state-sweep variant: 0 automatic, 1 simple per-node, 2 grouped LDS */
     int32_t tile[4];           /* 0 = automatic; tile[0] = SoC rows per workgroup (4, 8, 16),
-                                  tile[1] = workgroups sharing one node tile (control slices, <= 16) */
+                                  tile[1] = workgroups sharing one node tile (control slices, <= 16),
+                                  tile[2] = resident sweep workgroups per CU (capped by LDS), tile[3] = 0 */
+    const int32_t *inst_opt;   /* optional [n_inst][4] per-instance {kernel, tile[0], tile[1], tile[2]},
+                                  same meanings, 0 = the plan-wide value; NULL = none (e.g. the
+                                  choices of an autotuner for each problem shape)                   */
 } dp_options;
 
 typedef struct dp_plan dp_plan;
@@ -103,6 +110,11 @@ typedef struct {
     size_t traj_offset;        /* element (double) offset of its rollout rows in traj_dev          */
     size_t slab_elems;         /* n_v * n_soc * n_t                                                */
     int64_t evaluations;       /* N * slab_elems * n_u (dense state-control evaluations)           */
+    int32_t sweep_kernel;      /* state-sweep variant chosen: 1 simple per-node, 2 grouped LDS      */
+    int32_t sweep_tile;        /* SoC rows per workgroup (grouped sweep)                           */
+    int32_t sweep_split;       /* control slices per node tile (grouped sweep)                     */
+    int32_t sweep_grid;        /* persistent workgroups of one grouped-sweep launch                */
+    int32_t soc_shift;         /* host bound H on the SoC-cell shift of one step                   */
 } dp_instance_info;
 
 /* Validate n_inst problem descriptions, precompute host-side tables in FP64

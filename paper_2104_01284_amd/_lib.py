@@ -16,6 +16,7 @@ DP_OK, DP_EINVAL, DP_ENOMEM, DP_EDEVICE, DP_EINFEASIBLE, DP_ESTATE, DP_EUNSUPPOR
 DP_WAIT_AT_RED = 1
 DP_STORE_ALL_V = 1
 DP_TIMING = 2
+DP_GRAPH = 4
 
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_stage",
            "dp_rollout", "dp_adjoint", "dp_sweep_time", "dp_destroy", "dp_status_string", "dp_last_error")
@@ -41,13 +42,16 @@ class DpProblemDesc(C.Structure):
 
 
 class DpOptions(C.Structure):
-    _fields_ = [("flags", C.c_uint32), ("kernel", C.c_int32), ("tile", C.c_int32 * 4)]
+    _fields_ = [("flags", C.c_uint32), ("kernel", C.c_int32), ("tile", C.c_int32 * 4),
+                ("inst_opt", C.POINTER(C.c_int32))]
 
 
 class DpInstanceInfo(C.Structure):
     _fields_ = [("n_stages", C.c_int32), ("n_v", C.c_int32), ("n_soc", C.c_int32), ("n_t", C.c_int32),
                 ("n_u", C.c_int32), ("J_offset", C.c_size_t), ("pi_offset", C.c_size_t),
-                ("traj_offset", C.c_size_t), ("slab_elems", C.c_size_t), ("evaluations", C.c_int64)]
+                ("traj_offset", C.c_size_t), ("slab_elems", C.c_size_t), ("evaluations", C.c_int64),
+                ("sweep_kernel", C.c_int32), ("sweep_tile", C.c_int32), ("sweep_split", C.c_int32),
+                ("sweep_grid", C.c_int32), ("soc_shift", C.c_int32)]
 
 
 _lib = None

@@ -66,11 +66,14 @@ class Plan:
 
     ``Plan(instances, store_all=False, timing=False, device=0)`` validates the
     instances and uploads their parameter blocks; ``solve()`` runs the backward
-    recursion of every instance on the current torch stream.
+    recursion of every instance on the current torch stream, all instances in
+    rounds of one stage each.  ``graph=True`` records the solve once into a HIP
+    graph and replays it on later calls.
     """
 
     def __init__(self, instances, store_all: bool = False, timing: bool = False, device: int = 0,
-                 sweep_tile: int = 0, kernel: int = 0, split: int = 0):
+                 sweep_tile: int = 0, kernel: int = 0, split: int = 0, wg_per_cu: int = 0,
+                 graph: bool = False, inst_opts=None):
         import torch
         self.torch = torch
         if isinstance(instances, dict):
@@ -80,10 +83,20 @@ class Plan:
         self._descs = [_Desc(x) for x in self.instances]
         arr = (L.DpProblemDesc * len(self._descs))(*[x.d for x in self._descs])
         opt = L.DpOptions()
-        opt.flags = (L.DP_STORE_ALL_V if store_all else 0) | (L.DP_TIMING if timing else 0)
+        opt.flags = (L.DP_STORE_ALL_V if store_all else 0) | (L.DP_TIMING if timing else 0) | \
+            (L.DP_GRAPH if graph else 0)
         opt.tile[0] = int(sweep_tile)
         opt.tile[1] = int(split)
+        opt.tile[2] = int(wg_per_cu)
         opt.kernel = int(kernel)   # 0 automatic, 1 simple per-node sweep, 2 grouped LDS sweep
+        if inst_opts is not None:
+            # per instance (kernel, tile, split, wg_per_cu); 0 = the plan-wide value
+            io = np.zeros((len(self.instances), 4), dtype=np.int32)
+            for b, o in enumerate(inst_opts):
+                if o is not None:
+                    io[b, :len(o)] = o
+            self._inst_opts = np.ascontiguousarray(io)
+            opt.inst_opt = self._inst_opts.ctypes.data_as(C.POINTER(C.c_int32))
         self.store_all = store_all
         self.device = device
         h = C.c_void_p()

@@ -1,0 +1,105 @@
+"""Autotuner of the grouped state sweep.
+
+For one problem shape it times the candidate sweep configurations (SoC rows
+per workgroup of the grouped sweep) on a few stages of the instance and
+keeps the fastest.  The number of control slices stays with the
+library, which picks it per round of a batch.  Results are cached per
+(device, shape) in a JSON file, so a shape is timed once per machine.
+
+  opts = tuned_options(instances)          # one (kernel, tile, split, wg) per instance
+  plan = Plan(instances, inst_opts=opts)
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+# (kernel, SoC rows per workgroup) of the grouped sweep
+CANDIDATES = ((2, 16), (2, 8), (2, 4))
+
+
+def default_cache_path() -> str:
+    return os.environ.get("ECODP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ecodp", "sweep_tune.json"))
+
+
+def shape_key(inst: dict, device_name: str) -> str:
+    n_v, n_s, n_t = (int(inst[g][2]) for g in ("v_grid", "soc_grid", "t_grid"))
+    n_u = int(inst["te_grid"][2]) * int(inst["tm_grid"][2])
+    return f"{device_name}|v{n_v}|s{n_s}|t{n_t}|u{n_u}"
+
+
+def _time_config(inst, kernel, tile, stages, repeats, device):
+    import torch
+    from .api import Plan
+    plan = Plan([inst], timing=True, kernel=kernel, sweep_tile=tile, device=device)
+    info = plan.info[0]
+    if int(info.sweep_kernel) != kernel or int(info.sweep_tile) != tile:
+        return None
+    Jn = torch.zeros(plan.slab_shape(0), dtype=torch.float32, device=f"cuda:{device}")
+    for k in stages:                                  # warm-up
+        plan.stage(0, k, Jn)
+    torch.cuda.synchronize(device)
+    plan.sweep_time()
+    for _ in range(repeats):
+        for k in stages:
+            plan.stage(0, k, Jn)
+    torch.cuda.synchronize(device)
+    ms, n = plan.sweep_time()
+    return ms / max(1, n), int(info.soc_shift)
+
+
+def tune(inst: dict, device: int = 0, repeats: int = 3, candidates=CANDIDATES) -> dict:
+    """Time every candidate on three stages of `inst`; returns the fastest as
+    {"kernel", "tile", "ms", "all": {...}}."""
+    N = int(inst["N"])
+    stages = sorted({N - 1, N // 2, min(1, N - 1)})
+    n_s = int(inst["soc_grid"][2])
+    results = {}
+    for kernel, tile in candidates:
+        if tile > n_s and tile > 4:
+            continue
+        r = _time_config(inst, kernel, tile, stages, repeats, device)
+        if r is not None:
+            results[f"{kernel}/{tile}"] = r[0]
+    if not results:
+        return {"kernel": 0, "tile": 0, "ms": None, "all": {}}
+    best = min(results, key=results.get)
+    kernel, tile = (int(x) for x in best.split("/"))
+    return {"kernel": kernel, "tile": tile, "ms": results[best], "all": results}
+
+
+def tuned_options(instances, device: int = 0, cache_path: str | None = None, verbose: bool = False):
+    """Per-instance (kernel, tile, split, wg_per_cu) for Plan(inst_opts=...),
+    timing each shape not yet in the cache."""
+    import torch
+    path = cache_path or default_cache_path()
+    cache = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    name = torch.cuda.get_device_name(device)
+    out, dirty = [], False
+    for inst in instances:
+        key = shape_key(inst, name)
+        if key not in cache:
+            cache[key] = tune(inst, device)
+            dirty = True
+            if verbose:
+                print(f"[autotune] {key}: {cache[key]}", file=sys.stderr, flush=True)
+        c = cache[key]
+        out.append((int(c["kernel"]), int(c["tile"]), 0, 0))
+    if dirty:
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        except OSError:
+            pass
+    return out

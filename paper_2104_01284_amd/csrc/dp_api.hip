@@ -44,15 +44,39 @@ struct Inst {
     size_t S = 0;              // slab elements
     std::vector<int> light_of_stage;
     size_t J_off = 0, pi_off = 0, traj_off = 0;
-    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_batj = 0, scr_hdr = 0;
+    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_batj = 0;
     int sweep = 0;             // 1 = simple per-node kernel, 2 = grouped LDS kernel
     int jt = 8;                // SoC rows per workgroup of the grouped kernel
-    int nsplit = 1;            // workgroups sharing one (speed node, SoC tile), each a slice of the controls
-    size_t scr_pv = 0, scr_pu = 0, scr_rec = 0, scr_q = 0;
-    int grid = 0;              // persistent workgroups of the grouped sweep
+    int nsplit = 1;            // largest number of control slices of any of its stages
+    int split_opt = 0;         // caller's control slices (0 = chosen per round)
+    int wg_opt = 0;            // caller's resident sweep workgroups per CU (0 = by LDS)
+    size_t scr_pv = 0, scr_pu = 0, scr_rec = 0;
+    int grid = 0;              // persistent workgroups of a grouped sweep of this instance alone
     int H = 0;                 // bound on the SoC-cell shift of one step
     size_t tl_dev_off = 0;     // offset (entries) of this instance's TL table in the plan's TL array
     int64_t evals = 0;
+    std::vector<int> job_of_k; // grouped sweep: index of the (instance, k) job in the plan's job table
+};
+
+// One grouped-sweep launch of a round: the jobs of one (tile, pitch, block)
+// class, largest work per item first.
+struct SweepLaunch {
+    int jt = 0, pitch = 0, threads = 0;
+    int job_begin = 0, njobs = 0, items = 0, grid = 0;
+    size_t lds = 0;
+    size_t ib_off = 0;         // first entry of the launch's item_begin table
+    int q_slot = 0;            // queue counters
+    double work = 0.0;         // estimated lane-steps, for ordering the launches of a round
+};
+
+// Round r of a solve holds stage N_b - 1 - r of every instance b with N_b > r.
+struct Round {
+    int job_begin = 0, njobs = 0;      // grouped-sweep jobs, ordered by launch
+    int max_nv = 0;
+    long max_records = 0, max_nodes = 0;
+    bool any_split = false;
+    std::vector<SweepLaunch> sweeps;
+    std::vector<int> simple;           // instances on the simple per-node sweep
 };
 
 }  // namespace
@@ -69,6 +93,24 @@ struct dp_plan {
     bool solved = false;
     std::vector<hipEvent_t> ev;      // DP_TIMING: begin/end pairs of sweep launches
     int n_ev_used = 0;
+    // grouped sweep tables: parameter blocks, jobs, per-launch item offsets
+    std::vector<StageJob> jobs;
+    std::vector<Round> rounds;
+    void *dev_tables = nullptr;
+    DevInst *dev_insts = nullptr;
+    StageJob *dev_jobs = nullptr;
+    int *dev_ib = nullptr;
+    size_t scr_q = 0;                // 8 queue counters per sweep launch, then 8 for dp_stage
+    int n_q_slots = 0;
+    // independent sweep launches of a round run on these streams side by side
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[kSide] = {nullptr, nullptr, nullptr};
+    // DP_GRAPH: the captured solve and the buffers it was captured with
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void *graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -227,12 +269,188 @@ int dp_last_error(char *buf, size_t n)
     return DP_OK;
 }
 
+// Rounds of the batched solve.  Round r holds stage N_b - 1 - r of every
+// instance b with N_b > r, so one launch per kernel serves all instances of
+// a round.  Grouped-sweep jobs are grouped by kernel class (SoC tile, LDS
+// pitch, block size) and put in decreasing order of work per item, so the
+// longest items are taken first.  Control slices are chosen per round: a
+// round with few (speed node, tile) pairs is split until it has about eight
+// items per CU.  Appends the partial-result buffers and the queue counters to
+// the scratch layout and uploads the tables.
+static int plan_rounds(dp_plan *p, size_t scr)
+{
+    const int n_inst = (int)p->inst.size();
+    int maxN = 0;
+    for (const Inst &I : p->inst) maxN = std::max(maxN, I.N);
+    p->rounds.assign(maxN, Round{});
+    std::vector<int> ib;
+    int q_slot = 0;
+    const long target = 8L * p->n_cu;
+    for (int r = 0; r < maxN; r++) {
+        Round &R = p->rounds[r];
+        long base = 0;
+        std::vector<int> members;
+        for (int b = 0; b < n_inst; b++) {
+            const Inst &I = p->inst[b];
+            if (I.N <= r) continue;
+            if (I.sweep == 2) {
+                members.push_back(b);
+                base += (long)I.P.n_v * ((I.P.n_s + I.jt - 1) / I.jt);
+            } else {
+                R.simple.push_back(b);
+            }
+        }
+        const int ns_round = (int)std::min<long>(16, std::max<long>(1, (target + base - 1) / std::max(1L, base)));
+        struct Tmp { int b, cls_jt, cls_pitch, cls_threads, ns; double cost; };
+        std::vector<Tmp> t;
+        for (int b : members) {
+            Inst &I = p->inst[b];
+            int ns = I.split_opt > 0 ? I.split_opt : ns_round;
+            ns = std::max(1, std::min(ns, std::min(16, I.P.n_u)));
+            I.nsplit = std::max(I.nsplit, ns);
+            const int pitch = ((I.P.n_t + 63) / 64) * 64;
+            const int threads = 64 * ((I.P.n_t + 62) / 63);
+            t.push_back({b, I.jt, pitch, threads, ns, (double)I.P.n_u / ns});
+        }
+        std::stable_sort(t.begin(), t.end(), [](const Tmp &x, const Tmp &y) {
+            if (x.cls_jt != y.cls_jt) return x.cls_jt > y.cls_jt;
+            if (x.cls_pitch != y.cls_pitch) return x.cls_pitch > y.cls_pitch;
+            if (x.cls_threads != y.cls_threads) return x.cls_threads > y.cls_threads;
+            return x.cost > y.cost;
+        });
+        R.job_begin = (int)p->jobs.size();
+        R.njobs = (int)t.size();
+        for (size_t q = 0; q < t.size(); q++) {
+            Inst &I = p->inst[t[q].b];
+            const int k = I.N - 1 - r;
+            StageJob j;
+            std::memset(&j, 0, sizeof j);
+            j.inst = t[q].b;
+            j.k = k;
+            j.jt = I.jt;
+            j.ntiles = (I.P.n_s + I.jt - 1) / I.jt;
+            j.nsplit = t[q].ns;
+            j.H = I.H;
+            j.rw = I.jt + 2 * I.H + 2;
+            j.nitems = I.P.n_v * j.ntiles * j.nsplit;
+            const int L = I.light_of_stage[k];
+            j.tl = L >= 0 ? (int)(I.tl_dev_off + (size_t)L * I.P.n_t) : -1;
+            const bool all = (p->flags & DP_STORE_ALL_V) != 0;
+            j.jn = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k + 1 : ((k + 1) & 1)));
+            j.jk = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k : (k & 1)));
+            j.pik = (long long)(I.pi_off + sizeof(int16_t) * I.S * (size_t)k);
+            j.st = (long long)I.scr_st;
+            j.nf = (long long)I.scr_nf;
+            j.batj = (long long)I.scr_batj;
+            j.rec = (long long)I.scr_rec;
+            if (I.job_of_k.empty()) I.job_of_k.assign(I.N, -1);
+            I.job_of_k[k] = (int)p->jobs.size();
+            p->jobs.push_back(j);
+            R.max_nv = std::max(R.max_nv, I.P.n_v);
+            R.max_records = std::max(R.max_records, (long)I.P.n_v * I.P.n_u * j.ntiles);
+            R.max_nodes = std::max(R.max_nodes, (long)I.S);
+            R.any_split = R.any_split || j.nsplit > 1;
+            // a new launch starts where the class changes
+            if (q == 0 || t[q].cls_jt != t[q - 1].cls_jt || t[q].cls_pitch != t[q - 1].cls_pitch ||
+                t[q].cls_threads != t[q - 1].cls_threads) {
+                SweepLaunch L2;
+                L2.jt = t[q].cls_jt;
+                L2.pitch = t[q].cls_pitch;
+                L2.threads = t[q].cls_threads;
+                L2.job_begin = R.job_begin + (int)q;
+                L2.q_slot = q_slot++;
+                R.sweeps.push_back(L2);
+            }
+            SweepLaunch &S = R.sweeps.back();
+            S.njobs++;
+            S.items += j.nitems;
+            S.work += (double)j.nitems * ((double)I.P.n_u / j.nsplit) * I.jt * t[q].cls_threads;
+            S.lds = std::max(S.lds, lds_sweep_bytes(I.jt, I.H, I.P.n_t));
+        }
+        for (SweepLaunch &S : R.sweeps) {
+            S.lds += lds_job_index_bytes(S.njobs);
+            size_t wg = (size_t)p->lds_per_cu / S.lds;
+            const int waves = S.threads / 64;
+            if (wg * waves > 32) wg = 32 / waves;
+            // the smallest per-CU workgroup count any job of the launch asks for
+            for (int q = 0; q < S.njobs; q++) {
+                const int w = p->inst[p->jobs[S.job_begin + q].inst].wg_opt;
+                if (w > 0 && (size_t)w < wg) wg = w;
+            }
+            if (wg < 1) wg = 1;
+            S.grid = (int)(wg * (size_t)p->n_cu);
+            S.ib_off = ib.size();
+            int run = 0;
+            for (int q = 0; q < S.njobs; q++) {
+                ib.push_back(run);
+                run += p->jobs[S.job_begin + q].nitems;
+            }
+            ib.push_back(run);
+        }
+        // largest launch first: it starts on the main stream, the others beside it
+        std::stable_sort(R.sweeps.begin(), R.sweeps.end(),
+                         [](const SweepLaunch &x, const SweepLaunch &y) { return x.work > y.work; });
+    }
+    // partial results of control slices, sized for the largest slice count
+    for (Inst &I : p->inst) {
+        if (I.sweep != 2 || I.nsplit <= 1) continue;
+        I.scr_pv = scr;
+        scr += align_up(sizeof(float) * I.S * I.nsplit, 256);
+        I.scr_pu = scr;
+        scr += align_up(sizeof(int16_t) * I.S * I.nsplit, 256);
+    }
+    for (StageJob &j : p->jobs) {
+        j.pv = (long long)p->inst[j.inst].scr_pv;
+        j.pu = (long long)p->inst[j.inst].scr_pu;
+    }
+    p->n_q_slots = q_slot + 1;
+    p->scr_q = scr;
+    scr += align_up(sizeof(int) * 8 * (size_t)p->n_q_slots, 256);
+    p->bytes_scratch = scr;
+
+    const size_t b_inst = align_up(sizeof(DevInst) * n_inst, 256);
+    const size_t b_jobs = align_up(sizeof(StageJob) * std::max<size_t>(1, p->jobs.size()), 256);
+    const size_t b_ib = align_up(sizeof(int) * std::max<size_t>(1, ib.size()), 256);
+    hipError_t e = hipMalloc(&p->dev_tables, b_inst + b_jobs + b_ib);
+    if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu table bytes: %s", b_inst + b_jobs + b_ib,
+                                     hipGetErrorString(e));
+    std::vector<unsigned char> host(b_inst + b_jobs + b_ib, 0);
+    for (int b = 0; b < n_inst; b++) std::memcpy(host.data() + sizeof(DevInst) * b, &p->inst[b].P, sizeof(DevInst));
+    if (!p->jobs.empty()) std::memcpy(host.data() + b_inst, p->jobs.data(), sizeof(StageJob) * p->jobs.size());
+    if (!ib.empty()) std::memcpy(host.data() + b_inst + b_jobs, ib.data(), sizeof(int) * ib.size());
+    char *d = (char *)p->dev_tables;
+    p->dev_insts = (DevInst *)d;
+    p->dev_jobs = (StageJob *)(d + b_inst);
+    p->dev_ib = (int *)(d + b_inst + b_jobs);
+    if ((e = hipMemcpy(p->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "table upload");
+    return DP_OK;
+}
+
 int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_options *opt, int device, dp_plan **out)
 {
     if (!out) return fail(DP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!desc || n_inst < 1) return fail(DP_EINVAL, "need at least one problem description");
-    if (opt && (opt->flags & ~(DP_STORE_ALL_V | DP_TIMING))) return fail(DP_EINVAL, "unknown option flags");
+    if (opt && (opt->flags & ~(DP_STORE_ALL_V | DP_TIMING | DP_GRAPH))) return fail(DP_EINVAL, "unknown option flags");
+    if (opt && (opt->flags & DP_GRAPH) && (opt->flags & DP_TIMING))
+        return fail(DP_EINVAL, "option flags DP_GRAPH and DP_TIMING exclude each other");
+    if (n_inst > 1024) return fail(DP_EUNSUPPORTED, "at most 1024 instances per plan");
+    auto check_opt = [](int kernel, const int32_t *t, bool t3) -> int {
+        if (kernel < 0 || kernel > 2) return fail(DP_EINVAL, "unknown sweep kernel %d", kernel);
+        if (t[0] != 0 && t[0] != 4 && t[0] != 8 && t[0] != 16) return fail(DP_EINVAL, "tile[0] must be 0, 4, 8 or 16");
+        if (t[1] < 0 || t[1] > 16 || t[2] < 0 || t[2] > 32 || (t3 && t[3] != 0))
+            return fail(DP_EINVAL, "tile[1] must be in [0, 16], tile[2] in [0, 32], tile[3] zero");
+        return DP_OK;
+    };
+    if (opt) {
+        int rc = check_opt(opt->kernel, opt->tile, true);
+        if (rc) return rc;
+        if (opt->inst_opt)
+            for (int b = 0; b < n_inst; b++)
+                if ((rc = check_opt(opt->inst_opt[4 * b], opt->inst_opt + 4 * b + 1, false)))
+                    return fail(rc, "instance %d: %s", b, std::string(g_last_error).c_str());
+    }
     for (int b = 0; b < n_inst; b++) {
         int rc = validate(desc[b], b);
         if (rc) return rc;
@@ -400,8 +618,13 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             return (double)(wg * waves) / 4.0;
         };
         int jt = 0;
-        if (p->opt.tile[0] == 4 || p->opt.tile[0] == 8 || p->opt.tile[0] == 16) {
-            jt = p->opt.tile[0];
+        const int32_t *io = p->opt.inst_opt ? p->opt.inst_opt + 4 * b : nullptr;
+        const int o_kernel = io && io[0] ? io[0] : p->opt.kernel;
+        const int o_tile = io && io[1] ? io[1] : p->opt.tile[0];
+        I.split_opt = io && io[2] ? io[2] : p->opt.tile[1];
+        I.wg_opt = io && io[3] ? io[3] : p->opt.tile[2];
+        if (o_tile == 4 || o_tile == 8 || o_tile == 16) {
+            jt = o_tile;
         } else {
             const int cand[3] = {16, 8, 4};
             double best_w = 0.0;
@@ -419,11 +642,11 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             }
             if (jt == 0) jt = 4;
         }
-        const bool lds_fits = lds_sweep_bytes(jt, I.H, d.n_t) <= lds_cu && d.n_t <= 1008 && P.n_u <= 1024 &&
-                              d.n_v - 1 <= kSortBins;
+        const bool lds_fits = lds_sweep_bytes(jt, I.H, d.n_t) + lds_job_index_bytes(n_inst) <= lds_cu &&
+                              d.n_t <= 1008 && P.n_u <= 1024 && d.n_v - 1 <= kSortBins;
         I.jt = jt;
-        I.sweep = p->opt.kernel == 1 ? 1 : (lds_fits ? 2 : 1);
-        if (p->opt.kernel == 2 && !lds_fits) {
+        I.sweep = o_kernel == 1 ? 1 : (lds_fits ? 2 : 1);
+        if (o_kernel == 2 && !lds_fits) {
             (void)hipFree(p->dev_params);
             delete p;
             return fail(DP_EUNSUPPORTED, "instance %d: grouped sweep does not fit (n_t %d, n_u %d, H %d)", b, d.n_t,
@@ -432,6 +655,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         if (lds_fits) {
             size_t wg = lds_cu / lds_sweep_bytes(jt, I.H, d.n_t);
             if (wg * waves > 32) wg = 32 / waves;
+            if (I.wg_opt > 0 && (size_t)I.wg_opt < wg) wg = I.wg_opt;
             if (wg < 1) wg = 1;
             I.grid = (int)(wg * (size_t)p->n_cu);
         }
@@ -439,33 +663,15 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         scr += align_up(sizeof(SortedEntry) * d.n_v * P.n_u, 256);
         I.scr_nf = scr;
         scr += align_up(sizeof(int) * d.n_v, 256);
-        I.scr_bat = scr;   // BatEntry (simple kernel) or float2 weights (grouped kernel)
-        scr += align_up(sizeof(BatEntry) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
         if (I.sweep == 2) {
             const size_t ntiles = (d.n_soc + I.jt - 1) / I.jt;
-            // enough workgroups for 256 CUs: split the control list when the
-            // (speed node, SoC tile) grid alone is small
-            const long base_wg = (long)d.n_v * (long)ntiles;
-            int ns = (int)((2048 + base_wg - 1) / base_wg);
-            if (p->opt.tile[1] > 0) ns = p->opt.tile[1];
-            if (ns > 16) ns = 16;
-            if (ns > P.n_u) ns = P.n_u;
-            if (ns < 1) ns = 1;
-            I.nsplit = ns;
-            if (ns > 1) {
-                I.scr_pv = scr;
-                scr += align_up(sizeof(float) * I.S * ns, 256);
-                I.scr_pu = scr;
-                scr += align_up(sizeof(int16_t) * I.S * ns, 256);
-            }
-            I.scr_q = scr;
-            scr += align_up(sizeof(int) * 8 * (size_t)N, 256);
             I.scr_rec = scr;
             scr += align_up(sizeof(float) * (size_t)d.n_v * ntiles * P.n_u * (12 + 2 * I.jt), 256);
             I.scr_batj = scr;
             scr += align_up(sizeof(int) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
-            I.scr_hdr = scr;
-            scr += align_up(sizeof(int) * ((size_t)d.n_v * P.n_u * ntiles + 16), 256);
+        } else {
+            I.scr_bat = scr;
+            scr += align_up(sizeof(BatEntry) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
         }
         I.scr_rho = scr;
         scr += align_up(sizeof(double) * I.S * 2, 256);
@@ -473,11 +679,34 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
     }
     p->bytes_J = J_off;
     p->bytes_pi = pi_off;
-    p->bytes_scratch = scr;
     if ((e = hipMemcpy(p->dev_params, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess) {
         (void)hipFree(p->dev_params);
         delete p;
         return hip_fail(e, "parameter upload");
+    }
+    int rc = plan_rounds(p, scr);
+    if (rc) {
+        dp_destroy(p);
+        return rc;
+    }
+    if (p->flags & DP_GRAPH) {
+        if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+            dp_destroy(p);
+            return hip_fail(e, "capture stream");
+        }
+    }
+    bool multi = false;
+    for (const Round &R : p->rounds) multi = multi || R.sweeps.size() > 1;
+    if (multi) {
+        e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        for (int q = 0; q < dp_plan::kSide && e == hipSuccess; q++) {
+            e = hipStreamCreateWithFlags(&p->side[q], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[q], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            dp_destroy(p);
+            return hip_fail(e, "side streams");
+        }
     }
     *out = p;
     return DP_OK;
@@ -507,6 +736,11 @@ int dp_instance_info_get(const dp_plan *p, int32_t inst, dp_instance_info *info)
     info->traj_offset = I.traj_off;
     info->slab_elems = I.S;
     info->evaluations = I.evals;
+    info->sweep_kernel = I.sweep;
+    info->sweep_tile = I.jt;
+    info->sweep_split = I.nsplit;
+    info->sweep_grid = I.grid;
+    info->soc_shift = I.H;
     return DP_OK;
 }
 
@@ -516,50 +750,134 @@ static float *slab_ptr(dp_plan *p, const Inst &I, void *J, int k)
     return (float *)((char *)J + I.J_off) + (size_t)idx * I.S;
 }
 
-static int enqueue_stage(dp_plan *p, const Inst &I, int k, const float *Jn, float *Jk, int16_t *pik, void *scratch,
-                         hipStream_t s, bool zero_queue)
+static int time_begin(dp_plan *p, hipStream_t s)
+{
+    if (!(p->flags & DP_TIMING)) return DP_OK;
+    if (p->n_ev_used + 2 > (int)p->ev.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+            return fail(DP_EDEVICE, "event creation failed");
+        p->ev.push_back(a);
+        p->ev.push_back(b);
+    }
+    (void)hipEventRecord(p->ev[p->n_ev_used], s);
+    return DP_OK;
+}
+
+static void time_end(dp_plan *p, hipStream_t s)
+{
+    if (!(p->flags & DP_TIMING)) return;
+    (void)hipEventRecord(p->ev[p->n_ev_used + 1], s);
+    p->n_ev_used += 2;
+}
+
+static StageBase stage_base(dp_plan *p, void *J, void *pi, void *scratch)
+{
+    StageBase B;
+    B.insts = p->dev_insts;
+    B.jobs = p->dev_jobs;
+    B.J = (char *)J;
+    B.pi = (char *)pi;
+    B.scr = (char *)scratch;
+    B.tl = p->dev_tl;
+    B.Jn = nullptr;
+    B.Jk = nullptr;
+    B.pik = nullptr;
+    return B;
+}
+
+// Stage k of an instance on the simple per-node sweep.
+static int enqueue_simple(dp_plan *p, const Inst &I, int k, const float *Jn, float *Jk, int16_t *pik, void *scratch,
+                          hipStream_t s)
 {
     StageEntry *st = (StageEntry *)((char *)scratch + I.scr_st);
-    SortedEntry *sst = (SortedEntry *)((char *)scratch + I.scr_st);
-    int *nfeas = (int *)((char *)scratch + I.scr_nf);
     BatEntry *bat = (BatEntry *)((char *)scratch + I.scr_bat);
     const int L = I.light_of_stage[k];
     const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
-    float2 *batw = (float2 *)((char *)scratch + I.scr_bat);
-    int *batj = (int *)((char *)scratch + I.scr_batj);
-    int *hdr = (int *)((char *)scratch + I.scr_hdr);
-    if (I.sweep == 2) {
-        if (zero_queue && launch_fill_i32((int *)((char *)scratch + I.scr_q) + 8 * k, 8, 0, s))
-            return hip_fail(hipGetLastError(), "queue reset launch");
-        if (launch_stage_sorted(I.P, k, I.jt, sst, nfeas, batw, batj, hdr, (float *)((char *)scratch + I.scr_rec), s))
-            return hip_fail(hipGetLastError(), "stage table launch");
-    } else {
-        if (launch_stage_table(I.P, k, st, bat, s)) return hip_fail(hipGetLastError(), "stage table launch");
+    if (launch_stage_table(I.P, k, st, bat, s)) return hip_fail(hipGetLastError(), "stage table launch");
+    int rc = time_begin(p, s);
+    if (rc) return rc;
+    if (launch_sweep(I.P, k, Jn, Jk, pik, st, bat, tl, s)) return hip_fail(hipGetLastError(), "sweep launch");
+    time_end(p, s);
+    return DP_OK;
+}
+
+static int *queue_slot(dp_plan *p, void *scratch, int slot)
+{
+    return (int *)((char *)scratch + p->scr_q) + 8 * (size_t)slot;
+}
+
+// The terminal slabs, every round of stages, then the exact root step.
+static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev, hipStream_t s)
+{
+    for (size_t b = 0; b < p->inst.size(); b++) {
+        const Inst &I = p->inst[b];
+        if (launch_terminal(I.P, slab_ptr(p, I, J, I.N), s)) return hip_fail(hipGetLastError(), "terminal launch");
     }
-    const bool timing = (p->flags & DP_TIMING) != 0;
-    if (timing) {
-        if (p->n_ev_used + 2 > (int)p->ev.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-                return fail(DP_EDEVICE, "event creation failed");
-            p->ev.push_back(a);
-            p->ev.push_back(b);
+    if (launch_fill_i32(queue_slot(p, scratch, 0), 8L * p->n_q_slots, 0, s))
+        return hip_fail(hipGetLastError(), "queue reset launch");
+    const StageBase base = stage_base(p, J, pi, scratch);
+    for (size_t r = 0; r < p->rounds.size(); r++) {
+        const Round &R = p->rounds[r];
+        for (int b : R.simple) {
+            const Inst &I = p->inst[b];
+            const int k = I.N - 1 - (int)r;
+            int16_t *pik = (int16_t *)((char *)pi + I.pi_off) + (size_t)k * I.S;
+            int rc = enqueue_simple(p, I, k, slab_ptr(p, I, J, k + 1), slab_ptr(p, I, J, k), pik, scratch, s);
+            if (rc) return rc;
         }
-        (void)hipEventRecord(p->ev[p->n_ev_used], s);
+        if (R.njobs == 0) continue;
+        StageBase B = base;
+        B.jobs = p->dev_jobs + R.job_begin;
+        if (launch_stage_jobs(B, R.njobs, R.max_nv, R.max_records, s))
+            return hip_fail(hipGetLastError(), "stage table launch");
+        // launches of different kernel classes are independent: without
+        // DP_TIMING they run side by side on the plan's streams, so one
+        // launch's tail overlaps the next one's start
+        const int nside = (p->flags & DP_TIMING) ? 0 : std::min<int>(dp_plan::kSide, (int)R.sweeps.size() - 1);
+        if (nside > 0) {
+            hipError_t e = hipEventRecord(p->fork, s);
+            for (int q = 0; q < nside && e == hipSuccess; q++) e = hipStreamWaitEvent(p->side[q], p->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "stream fork");
+        }
+        for (size_t q = 0; q < R.sweeps.size(); q++) {
+            const SweepLaunch &S = R.sweeps[q];
+            hipStream_t ls = (nside > 0 && q % (nside + 1) != 0) ? p->side[q % (nside + 1) - 1] : s;
+            StageBase Bs = base;
+            Bs.jobs = p->dev_jobs + S.job_begin;
+            int rc = time_begin(p, ls);
+            if (rc) return rc;
+            if (launch_sweep_jobs(S.jt, S.pitch, S.threads, Bs, S.njobs, p->dev_ib + S.ib_off, S.items,
+                                  queue_slot(p, scratch, S.q_slot), S.grid, S.lds, ls))
+                return hip_fail(hipGetLastError(), "sweep launch");
+            time_end(p, ls);
+        }
+        if (nside > 0) {
+            hipError_t e = hipSuccess;
+            for (int q = 0; q < nside && e == hipSuccess; q++) {
+                e = hipEventRecord(p->join[q], p->side[q]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join[q], 0);
+            }
+            if (e != hipSuccess) return hip_fail(e, "stream join");
+        }
+        if (R.any_split && launch_combine_jobs(B, R.njobs, R.max_nodes, s))
+            return hip_fail(hipGetLastError(), "combine launch");
     }
-    float *part_v = (float *)((char *)scratch + I.scr_pv);
-    int16_t *part_u = (int16_t *)((char *)scratch + I.scr_pu);
-    int *queue = (int *)((char *)scratch + I.scr_q) + 8 * k;
-    const int rc = I.sweep == 2 ? launch_sweep_lds(I.jt, I.P, k, Jn, Jk, pik, nfeas,
-                                                   (const float *)((char *)scratch + I.scr_rec), batj, tl, I.H,
-                                                   I.nsplit, part_v, part_u, queue, I.grid, s)
-                                : launch_sweep(I.P, k, Jn, Jk, pik, st, bat, tl, s);
-    if (rc) return hip_fail(hipGetLastError(), "sweep launch");
-    if (timing) {
-        (void)hipEventRecord(p->ev[p->n_ev_used + 1], s);
-        p->n_ev_used += 2;
+    for (size_t b = 0; b < p->inst.size(); b++) {
+        const Inst &I = p->inst[b];
+        if (launch_root(I.P, slab_ptr(p, I, J, 1), V0_dev + b, u0_dev + b, s))
+            return hip_fail(hipGetLastError(), "root launch");
     }
     return DP_OK;
+}
+
+static void drop_graph(dp_plan *p)
+{
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    for (int q = 0; q < 5; q++) p->graph_key[q] = nullptr;
 }
 
 int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev, void *stream)
@@ -569,19 +887,36 @@ int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    for (size_t b = 0; b < p->inst.size(); b++) {
-        const Inst &I = p->inst[b];
-        if (launch_terminal(I.P, slab_ptr(p, I, J, I.N), s)) return hip_fail(hipGetLastError(), "terminal launch");
-        if (I.sweep == 2 && launch_fill_i32((int *)((char *)scratch + I.scr_q), 8L * I.N, 0, s))
-            return hip_fail(hipGetLastError(), "queue reset launch");
-        for (int k = I.N - 1; k >= 0; k--) {
-            int16_t *pik = (int16_t *)((char *)pi + I.pi_off) + (size_t)k * I.S;
-            int rc = enqueue_stage(p, I, k, slab_ptr(p, I, J, k + 1), slab_ptr(p, I, J, k), pik, scratch, s, false);
-            if (rc) return rc;
-        }
-        if (launch_root(I.P, slab_ptr(p, I, J, 1), V0_dev + b, u0_dev + b, s))
-            return hip_fail(hipGetLastError(), "root launch");
+    if (!(p->flags & DP_GRAPH)) {
+        int rc = enqueue_solve(p, J, pi, scratch, V0_dev, u0_dev, s);
+        if (rc) return rc;
+        p->solved = true;
+        return DP_OK;
     }
+    const void *key[5] = {J, pi, scratch, V0_dev, u0_dev};
+    bool same = p->graph_exec != nullptr;
+    for (int q = 0; q < 5; q++) same = same && key[q] == p->graph_key[q];
+    if (!same) {
+        drop_graph(p);
+        if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        const int rc = enqueue_solve(p, J, pi, scratch, V0_dev, u0_dev, p->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->cap_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        p->graph = g;
+        if ((e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            p->graph_exec = nullptr;
+            drop_graph(p);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        for (int q = 0; q < 5; q++) p->graph_key[q] = key[q];
+    }
+    if ((e = hipGraphLaunch(p->graph_exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     p->solved = true;
     return DP_OK;
 }
@@ -597,7 +932,28 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
     if (J_next == J_out) return fail(DP_EINVAL, "J_next and J_out must not alias");
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    return enqueue_stage(p, I, k, J_next, J_out, pi_out, scratch, (hipStream_t)stream, true);
+    hipStream_t s = (hipStream_t)stream;
+    if (I.sweep != 2) return enqueue_simple(p, I, k, J_next, J_out, pi_out, scratch, s);
+    const int idx = I.job_of_k[k];
+    const StageJob &j = p->jobs[idx];
+    StageBase B = stage_base(p, nullptr, nullptr, scratch);
+    B.jobs = p->dev_jobs + idx;
+    B.Jn = J_next;
+    B.Jk = J_out;
+    B.pik = pi_out;
+    int *q = queue_slot(p, scratch, p->n_q_slots - 1);
+    if (launch_fill_i32(q, 8, 0, s)) return hip_fail(hipGetLastError(), "queue reset launch");
+    if (launch_stage_jobs(B, 1, I.P.n_v, (long)I.P.n_v * I.P.n_u * j.ntiles, s))
+        return hip_fail(hipGetLastError(), "stage table launch");
+    int rc = time_begin(p, s);
+    if (rc) return rc;
+    const int pitch = ((I.P.n_t + 63) / 64) * 64, threads = 64 * ((I.P.n_t + 62) / 63);
+    if (launch_sweep_jobs(I.jt, pitch, threads, B, 1, nullptr, j.nitems, q, I.grid,
+                          lds_sweep_bytes(I.jt, I.H, I.P.n_t), s))
+        return hip_fail(hipGetLastError(), "sweep launch");
+    time_end(p, s);
+    if (j.nsplit > 1 && launch_combine_jobs(B, 1, (long)I.S, s)) return hip_fail(hipGetLastError(), "combine launch");
+    return DP_OK;
 }
 
 int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_dev, int32_t *status_dev, void *stream)
@@ -677,6 +1033,14 @@ void dp_destroy(dp_plan *p)
     if (!p) return;
     (void)hipSetDevice(p->device);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    drop_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (int q = 0; q < dp_plan::kSide; q++) {
+        if (p->side[q]) (void)hipStreamDestroy(p->side[q]);
+        if (p->join[q]) (void)hipEventDestroy(p->join[q]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->dev_tables) (void)hipFree(p->dev_tables);
     if (p->dev_params) (void)hipFree(p->dev_params);
     delete p;
 }

@@ -13,12 +13,13 @@ int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *p
                  const BatEntry *bat, const TLEntry *tl, hipStream_t s);
 int launch_root(const DevInst &P, const float *J1, float *V0, int16_t *u0, hipStream_t s);
 
-int launch_stage_sorted(const DevInst &P, int k, int JT, SortedEntry *st, int *nfeas, float2 *batw, int *batj,
-                        int *hdr, float *rec, hipStream_t s);
+// Grouped sweep over a table of (instance, stage) jobs.
+int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_records, hipStream_t s);
 size_t lds_sweep_bytes(int JT, int H, int n_t);
-int launch_sweep_lds(int JT, const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const int *nfeas,
-                     const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit, float *part_v,
-                     int16_t *part_u, int *queue, int grid, hipStream_t s);
+size_t lds_job_index_bytes(int njobs);
+int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int njobs, const int *item_begin,
+                      int total, int *queue, int grid, size_t lds, hipStream_t s);
+int launch_combine_jobs(const StageBase &B, int njobs, long max_nodes, hipStream_t s);
 int launch_fill_i32(int *p, long n, int v, hipStream_t s);
 
 int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, const TLEntry *unused,

@@ -76,6 +76,38 @@ struct TLEntry {
     float pad;
 };
 
+// One (instance, stage) of the grouped sweep.  Buffer positions are byte
+// offsets from the J, pi and scratch pointers of the call, so one table built
+// with the plan serves every call.
+struct StageJob {
+    int inst;              // index of the instance's parameter block
+    int k;                 // stage
+    int jt;                // SoC rows per workgroup
+    int ntiles;            // SoC tiles
+    int nsplit;            // control slices per (speed node, tile)
+    int H;                 // bound on the SoC-cell shift of one step
+    int rw;                // staged SoC rows per plane (jt + 2H + 2)
+    int nitems;            // n_v * ntiles * nsplit sweep items
+    int tl;                // offset (entries) of the stage's signal table, -1 = none
+    int pad;
+    long long jn, jk, pik;                 // J_{k+1}, J_k (J buffer), pi_k (pi buffer)
+    long long st, nf, batj, rec, pv, pu;   // stage data and partial results (scratch)
+};
+
+// Launch-wide pointers of a set of jobs.  Jn / Jk / pik, when set, replace the
+// J and pi buffers of a single job (an isolated stage on caller slabs).
+struct StageBase {
+    const DevInst *insts;
+    const StageJob *jobs;
+    char *J;
+    char *pi;
+    char *scr;
+    const TLEntry *tl;
+    const float *Jn;
+    float *Jk;
+    int16_t *pik;
+};
+
 // Result of the continuous one-step model for (stage k, speed v, control).
 struct PT {
     double v1, acc, dt, cost, mf, Pb, q, Ftr, Froad, cosa, sina;

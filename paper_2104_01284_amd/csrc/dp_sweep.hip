@@ -22,15 +22,20 @@ namespace ecodp {
 
 // ------------------------------------------------------- sorted stage table --
 
-// One workgroup per speed node i, one thread per control: the FP64 powertrain
-// model (as the per-pair stage table) and a stable counting sort of the
-// feasible controls by successor speed cell.
-__global__ void __launch_bounds__(1024) k_stage_sort(DevInst P, int k, SortedEntry *__restrict__ out,
-                                                     int *__restrict__ nfeas)
+// One workgroup per (job, speed node i), one thread per control: the FP64
+// powertrain model (as the per-pair stage table) and a stable counting sort
+// of the feasible controls by successor speed cell.
+__global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
 {
     __shared__ int s_hist[kSortBins];
     __shared__ int s_min, s_max, s_cnt;
+    const StageJob &jb = B.jobs[blockIdx.y];
+    const DevInst &P = B.insts[jb.inst];
+    const int k = jb.k;
     const int i = blockIdx.x;
+    if (i >= P.n_v) return;
+    SortedEntry *__restrict__ out = (SortedEntry *)(B.scr + jb.st);
+    int *__restrict__ nfeas = (int *)(B.scr + jb.nf);
     const int u = threadIdx.x;
     const int nu = P.n_u;
     if (u == 0) {
@@ -133,10 +138,16 @@ __host__ __device__ constexpr int rec_words(int JT) { return 12 + 2 * JT; }
 // cell (also kept in batj for the general path) and the weights (fx, gx);
 // the header is the first node's cell when the tile's cells are consecutive
 // (jx0 + q), else -1.
-__global__ void k_stage_bat_sorted(DevInst P, int k, int JT, int ntiles, const SortedEntry *__restrict__ st,
-                                   const int *__restrict__ nfeas, int *__restrict__ batj, float *__restrict__ rec)
+__global__ void k_stage_bat_sorted(StageBase B)
 {
 #pragma clang fp contract(off)
+    const StageJob &jb = B.jobs[blockIdx.y];
+    const DevInst &P = B.insts[jb.inst];
+    const int k = jb.k, JT = jb.jt, ntiles = jb.ntiles;
+    const SortedEntry *__restrict__ st = (const SortedEntry *)(B.scr + jb.st);
+    const int *__restrict__ nfeas = (const int *)(B.scr + jb.nf);
+    int *__restrict__ batj = (int *)(B.scr + jb.batj);
+    float *__restrict__ rec = (float *)(B.scr + jb.rec);
     const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long total = (long)P.n_v * P.n_u * ntiles;
     if (idx >= total) return;
@@ -190,32 +201,38 @@ __device__ inline float shl1(float x)
 // Registers per thread that prefetch the next run of control records.
 constexpr int kPrefetch = 4;
 
+// The job and parameter tables come in as separate read-only arguments so
+// that their fields are loaded through the scalar unit.
 template <int JT, int PITCH>
-__global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const float *__restrict__ Jn,
-                                                    float *__restrict__ Jk, int16_t *__restrict__ pik,
-                                                    const int *__restrict__ nfeas, const float *__restrict__ rec,
-                                                    const int *__restrict__ batj, const TLEntry *__restrict__ tl,
-                                                    int H, int ntiles, int rw, int nsplit, float *__restrict__ part_v,
-                                                    int16_t *__restrict__ part_u, int *__restrict__ queue)
+__global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs,
+                                                    const DevInst *__restrict__ insts, int njobs,
+                                                    const int *__restrict__ item_begin, int total,
+                                                    int *__restrict__ queue)
 {
-    extern __shared__ float lds[];
+    extern __shared__ float lds_base[];
     constexpr int CW = rec_words(JT);
-    const int nt = P.n_t, ns = P.n_s, nu = P.n_u;
-    // Persistent workgroups take (speed node, SoC tile, control slice) items
-    // from eight queues, one contiguous band of speed nodes per XCD (blocks
+    // A launch covers the items of njobs jobs; item_begin[q] is the first
+    // item of job q (njobs + 1 entries, kept in LDS ahead of the planes).
+    int *s_ib = reinterpret_cast<int *>(lds_base);
+    const int ibw = item_begin ? ((njobs + 64) / 64) * 64 : 0;
+    if (item_begin)
+        for (int q = threadIdx.x; q <= njobs; q += blockDim.x) s_ib[q] = item_begin[q];
+    float *lds = lds_base + ibw;
+    // Persistent workgroups take (job, speed node, SoC tile, control slice)
+    // items from eight queues, one contiguous band of items per XCD (blocks
     // are dealt round-robin over the 8 XCDs, so a band stays in one L2); a
     // workgroup whose band is drained takes items from the other bands.
     // Every workgroup exits once all queues are drained.
-    __shared__ int s_item;
-    const int nitems = P.n_v * ntiles * nsplit;
+    __shared__ int s_item, s_job;
     const int home = blockIdx.x & 7;
     int qi = 0;
+    __syncthreads();
     for (;;) {
     if (threadIdx.x == 0) {
-        int item = -1;
+        int item = -1, job = 0;
         while (qi < 8) {
             const int x = (home + qi) & 7;
-            const int lo = (int)(((long)nitems * x) >> 3), hi = (int)(((long)nitems * (x + 1)) >> 3);
+            const int lo = (int)(((long)total * x) >> 3), hi = (int)(((long)total * (x + 1)) >> 3);
             const int got = lo + atomicAdd(&queue[x], 1);
             if (got < hi) {
                 item = got;
@@ -223,12 +240,49 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const fl
             }
             qi++;
         }
+        if (item >= 0 && item_begin) {
+            // the last job whose first item is <= item
+            int a = 0, b = njobs - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (s_ib[mid] <= item) a = mid;
+                else b = mid - 1;
+            }
+            job = a;
+            item -= s_ib[a];
+        }
         s_item = item;
+        s_job = job;
     }
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    const int jbi = __builtin_amdgcn_readfirstlane(s_job);
     __syncthreads();
     if (item < 0) break;
+    const StageJob &jb = jobs[jbi];
+    const DevInst &PI = insts[jb.inst];
+    SweepArgs P;
+    P.n_v = PI.n_v;
+    P.n_t = PI.n_t;
+    P.n_s = PI.n_s;
+    P.n_u = PI.n_u;
+    P.zero_row = PI.zero_row;
+    P.wait = PI.wait;
+    P.Jinf = (float)PI.Jinf;
+    P.v_lo = PI.v_lo;
+    P.hv = PI.hv;
+    P.vmax = PI.vmax;
+    const int k = jb.k, H = jb.H, ntiles = jb.ntiles, rw = jb.rw, nsplit = jb.nsplit;
+    const float *__restrict__ Jn = B.Jn ? B.Jn : (const float *)(B.J + jb.jn);
+    float *__restrict__ Jk = B.Jk ? B.Jk : (float *)(B.J + jb.jk);
+    int16_t *__restrict__ pik = B.pik ? B.pik : (int16_t *)(B.pi + jb.pik);
+    const int *__restrict__ nfeas = (const int *)(B.scr + jb.nf);
+    const float *__restrict__ rec = (const float *)(B.scr + jb.rec);
+    const int *__restrict__ batj = (const int *)(B.scr + jb.batj);
+    const TLEntry *__restrict__ tl = jb.tl >= 0 ? B.tl + jb.tl : nullptr;
+    float *__restrict__ part_v = (float *)(B.scr + jb.pv);
+    int16_t *__restrict__ part_u = (int16_t *)(B.scr + jb.pu);
+    const int nt = P.n_t, ns = P.n_s, nu = P.n_u;
     const int i = item / (ntiles * nsplit);
     const int rem = item - i * ntiles * nsplit;
     const int tile = rem / nsplit;
@@ -255,13 +309,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const fl
         v = P.v_lo + i * P.hv;
     }
     const bool row_ok = !(v > P.vmax[k]);
-    const int nf = row_ok ? nfeas[i] : 0;
+    const int nf = __builtin_amdgcn_readfirstlane(row_ok ? nfeas[i] : 0);
     const int r_begin = (int)(((long)nf * split) / nsplit);
     const int r_end = (int)(((long)nf * (split + 1)) / nsplit);
     const long SV = (long)ns * nt;
     const int slot_sz = rw * PITCH;              // floats per staged plane
     float *chunk = lds + 2 * slot_sz;             // kPrefetch * blockDim floats
-    const int cc = (kPrefetch * (int)blockDim.x) / CW;   // controls per staged run
+    const int cc = __builtin_amdgcn_readfirstlane((kPrefetch * (int)blockDim.x) / CW);   // controls per staged run
     const float *recs = rec + ((long)i * ntiles + tile) * nu * CW;
     int plane[2] = {-1, -1};
     int cur_p = -2;
@@ -285,7 +339,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const fl
         for (int q = 0; q < kPrefetch; q++) chunk[threadIdx.x + q * blockDim.x] = pre[q];
         __syncthreads();
         if (c0 + cc < r_end) fetch(c0 + cc);        // in flight while this run is processed
-        const int cn = min(cc, r_end - c0);
+        const int cn = __builtin_amdgcn_readfirstlane(min(cc, r_end - c0));
         for (int cr = 0; cr < cn; cr++) {
             const float *ce = chunk + cr * CW;
             const int p = __builtin_amdgcn_readfirstlane(__float_as_int(ce[5]));
@@ -347,7 +401,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const fl
                 const int r = c0 + cr;
 #pragma unroll
                 for (int q = 0; q < JT; q++) {
-                    const int jx = q < jc ? batj[((long)i * nu + r) * ns + j0 + q] : -1;
+                    const int jx = q < jc ? __builtin_amdgcn_readfirstlane(batj[((long)i * nu + r) * ns + j0 + q]) : -1;
                     Qv[q] = Jinf;
                     if (jx >= 0) {
                         float V0, V1;
@@ -420,11 +474,20 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(SweepArgs P, int k, const fl
 // Minimum over the control splits (the first split wins a tie, so the result
 // does not depend on the number of splits), then the signal override and the
 // store of J_k and pi_k.
-__global__ void k_sweep_combine(SweepArgs P, int nv, int nsplit, const float *__restrict__ part_v,
-                                const int16_t *__restrict__ part_u, const float *__restrict__ Jn,
-                                float *__restrict__ Jk, int16_t *__restrict__ pik, const TLEntry *__restrict__ tl)
+__global__ void k_sweep_combine(StageBase B)
 {
-    const long S = (long)nv * P.n_s * P.n_t;
+    const StageJob &jb = B.jobs[blockIdx.y];
+    const int nsplit = jb.nsplit;
+    if (nsplit <= 1) return;
+    const DevInst &P = B.insts[jb.inst];
+    const float *__restrict__ Jn = B.Jn ? B.Jn : (const float *)(B.J + jb.jn);
+    float *__restrict__ Jk = B.Jk ? B.Jk : (float *)(B.J + jb.jk);
+    int16_t *__restrict__ pik = B.pik ? B.pik : (int16_t *)(B.pi + jb.pik);
+    const TLEntry *__restrict__ tl = jb.tl >= 0 ? B.tl + jb.tl : nullptr;
+    const float *__restrict__ part_v = (const float *)(B.scr + jb.pv);
+    const int16_t *__restrict__ part_u = (const int16_t *)(B.scr + jb.pu);
+    const float Jinf = (float)P.Jinf;
+    const long S = (long)P.n_v * P.n_s * P.n_t;
     for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
         float J = part_v[n];
         int pu = part_u[n];
@@ -441,12 +504,12 @@ __global__ void k_sweep_combine(SweepArgs P, int nv, int nsplit, const float *__
             if (t.red) {
                 const long ij = n / P.n_t;
                 const int i = (int)(ij / P.n_s);
-                J = P.Jinf;
+                J = Jinf;
                 pu = -1;
                 if (i == P.zero_row && P.wait && t.wc >= 0) {
                     const float *pw = Jn + ij * P.n_t + t.wc;
                     const float w = t.wcost + (t.wg32 * pw[0] + t.wf32 * pw[1]);
-                    if (w < P.Jinf) {
+                    if (w < Jinf) {
                         J = w;
                         pu = -2;
                     }
@@ -460,32 +523,12 @@ __global__ void k_sweep_combine(SweepArgs P, int nv, int nsplit, const float *__
 
 // ----------------------------------------------------------------- launch --
 
-int launch_stage_sorted(const DevInst &P, int k, int JT, SortedEntry *st, int *nfeas, float2 *, int *batj, int *,
-                        float *rec, hipStream_t s)
+int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_records, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage_sort, dim3(P.n_v), dim3(1024), 0, s, P, k, st, nfeas);
+    hipLaunchKernelGGL(k_stage_sort, dim3(max_nv, njobs), dim3(1024), 0, s, B);
     if (hipGetLastError() != hipSuccess) return -1;
-    const int ntiles = (P.n_s + JT - 1) / JT;
-    const long total = (long)P.n_v * P.n_u * ntiles;
-    hipLaunchKernelGGL(k_stage_bat_sorted, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P, k, JT, ntiles,
-                       st, nfeas, batj, rec);
+    hipLaunchKernelGGL(k_stage_bat_sorted, dim3((unsigned)((max_records + 255) / 256), njobs), dim3(256), 0, s, B);
     return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-static SweepArgs sweep_args(const DevInst &P)
-{
-    SweepArgs a;
-    a.n_v = P.n_v;
-    a.n_t = P.n_t;
-    a.n_s = P.n_s;
-    a.n_u = P.n_u;
-    a.zero_row = P.zero_row;
-    a.wait = P.wait;
-    a.Jinf = (float)P.Jinf;
-    a.v_lo = P.v_lo;
-    a.hv = P.hv;
-    a.vmax = P.vmax;
-    return a;
 }
 
 size_t lds_sweep_bytes(int JT, int H, int n_t)
@@ -495,39 +538,18 @@ size_t lds_sweep_bytes(int JT, int H, int n_t)
     return sizeof(float) * (2 * (size_t)(JT + 2 * H + 2) * pitch + (size_t)kPrefetch * threads);
 }
 
-template <int JT, int PITCH>
-static int launch_lds_t(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const int *nfeas,
-                        const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit, float *part_v,
-                        int16_t *part_u, int *queue, int grid, hipStream_t s)
-{
-    const int ntiles = (P.n_s + JT - 1) / JT;
-    const int rw = JT + 2 * H + 2;
-    const int waves = (P.n_t + 62) / 63;
-    const size_t lds = lds_sweep_bytes(JT, H, P.n_t);
-    const int nitems = P.n_v * ntiles * nsplit;
-    hipLaunchKernelGGL((k_sweep_lds<JT, PITCH>), dim3(grid < nitems ? grid : nitems), dim3(64 * waves), lds, s,
-                       sweep_args(P), k, Jn, Jk, pik, nfeas, rec, batj, tl, H, ntiles, rw, nsplit, part_v, part_u,
-                       queue);
-    if (hipGetLastError() != hipSuccess) return -1;
-    if (nsplit > 1) {
-        const long S = (long)P.n_v * P.n_s * P.n_t;
-        long blocks = (S + 255) / 256;
-        if (blocks > 16384) blocks = 16384;
-        hipLaunchKernelGGL(k_sweep_combine, dim3((unsigned)blocks), dim3(256), 0, s, sweep_args(P), P.n_v, nsplit,
-                           part_v, part_u, Jn, Jk, pik, tl);
-        if (hipGetLastError() != hipSuccess) return -1;
-    }
-    return 0;
-}
+size_t lds_job_index_bytes(int njobs) { return njobs > 1 ? sizeof(int) * (size_t)(((njobs + 64) / 64) * 64) : 0; }
 
 template <int JT>
-static int launch_lds_p(int pitch, const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik,
-                        const int *nfeas, const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit,
-                        float *part_v, int16_t *part_u, int *queue, int grid, hipStream_t s)
+static int launch_sweep_p(int pitch, dim3 grid, dim3 block, size_t lds, hipStream_t s, const StageBase &B,
+                          int njobs, const int *item_begin, int total, int *queue)
 {
     switch (pitch) {
-#define ECODP_PITCH(X) \
-    case X: return launch_lds_t<JT, X>(P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue, grid, s);
+#define ECODP_PITCH(X)                                                                                        \
+    case X:                                                                                                   \
+        hipLaunchKernelGGL((k_sweep_lds<JT, X>), grid, block, lds, s, B, B.jobs, B.insts, njobs, item_begin, total, \
+                           queue);                                                                              \
+        return hipGetLastError() == hipSuccess ? 0 : -1;
         ECODP_PITCH(64)
         ECODP_PITCH(128)
         ECODP_PITCH(192)
@@ -549,19 +571,24 @@ static int launch_lds_p(int pitch, const DevInst &P, int k, const float *Jn, flo
     }
 }
 
-int launch_sweep_lds(int JT, const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const int *nfeas,
-                     const float *rec, const int *batj, const TLEntry *tl, int H, int nsplit, float *part_v,
-                     int16_t *part_u, int *queue, int grid, hipStream_t s)
+int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int njobs, const int *item_begin,
+                      int total, int *queue, int grid, size_t lds, hipStream_t s)
 {
-    const int pitch = ((P.n_t + 63) / 64) * 64;
-    if (JT == 16)
-        return launch_lds_p<16>(pitch, P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue,
-                                grid, s);
-    if (JT == 8)
-        return launch_lds_p<8>(pitch, P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue,
-                               grid, s);
-    return launch_lds_p<4>(pitch, P, k, Jn, Jk, pik, nfeas, rec, batj, tl, H, nsplit, part_v, part_u, queue, grid,
-                           s);
+    const dim3 g(grid < total ? grid : total), blk(threads);
+    if (njobs > 1 && !item_begin) return -2;
+    const int *ib = njobs > 1 ? item_begin : nullptr;
+    if (JT == 16) return launch_sweep_p<16>(pitch, g, blk, lds, s, B, njobs, ib, total, queue);
+    if (JT == 8) return launch_sweep_p<8>(pitch, g, blk, lds, s, B, njobs, ib, total, queue);
+    if (JT == 4) return launch_sweep_p<4>(pitch, g, blk, lds, s, B, njobs, ib, total, queue);
+    return -2;
+}
+
+int launch_combine_jobs(const StageBase &B, int njobs, long max_nodes, hipStream_t s)
+{
+    long blocks = (max_nodes + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_sweep_combine, dim3((unsigned)blocks, njobs), dim3(256), 0, s, B);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 __global__ void k_fill_i32(int *p, long n, int v)

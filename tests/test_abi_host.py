@@ -42,11 +42,14 @@ def test_status_strings(lib):
     assert lib.dp_status_string(-99) == b"unknown status"
 
 
-def build_rc(lib, inst, n=1, flags=0):
+def build_rc(lib, inst, n=1, flags=0, kernel=0, tile=(0, 0, 0, 0)):
     d = _Desc(inst)
     arr = (L.DpProblemDesc * n)(*([d.d] * n))
     opt = L.DpOptions()
     opt.flags = flags
+    opt.kernel = kernel
+    for q in range(4):
+        opt.tile[q] = tile[q]
     h = C.c_void_p()
     rc = lib.dp_build_problem(arr, n, C.byref(opt), 0, C.byref(h))
     if rc == 0:
@@ -107,3 +110,29 @@ def test_null_arguments(lib):
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU device node is present")
 def test_no_device_is_edevice(lib):
     assert build_rc(lib, ins.plain()) == L.DP_EDEVICE
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(flags=8), "flags"),
+    (dict(kernel=4), "kernel"),
+    (dict(flags=6), "exclude"),
+    (dict(kernel=-1), "kernel"),
+    (dict(tile=(5, 0, 0, 0)), "tile[0]"),
+    (dict(tile=(0, 17, 0, 0)), "tile[1]"),
+    (dict(tile=(0, 0, 33, 0)), "tile[2]"),
+    (dict(tile=(0, 0, 0, 1)), "tile[3]"),
+])
+def test_options_validated_before_device(lib, kw, needle):
+    assert build_rc(lib, ins.plain(), **kw) == L.DP_EINVAL
+    assert needle in last_error(lib)
+
+
+def test_per_instance_options_validated(lib):
+    d = _Desc(ins.plain())
+    arr = (L.DpProblemDesc * 2)(d.d, d.d)
+    io = np.array([[2, 8, 0, 0], [2, 5, 0, 0]], dtype=np.int32)
+    opt = L.DpOptions()
+    opt.inst_opt = io.ctypes.data_as(C.POINTER(C.c_int32))
+    h = C.c_void_p()
+    assert lib.dp_build_problem(arr, 2, C.byref(opt), 0, C.byref(h)) == L.DP_EINVAL
+    assert "instance 1" in last_error(lib) and "tile[0]" in last_error(lib)
