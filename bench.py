@@ -36,6 +36,9 @@ DESCR = {
 }
 
 
+PROFILE_NAME = {"realistic": "realistic_2km", "large": "large_3km", "plain": "plain_500m", "paper": "paper_shape"}
+
+
 def cpu_baseline(inst, budget_s: float):
     """The FP64 oracle's backward stages from J_N, timed on the host cores
     until the budget is spent (at least one stage)."""
@@ -57,6 +60,22 @@ def cpu_baseline(inst, budget_s: float):
             "kind": "oracle",
             "sample": f"{done} backward stages (k={inst['N'] - 1}..{inst['N'] - done}) of {inst['name']} "
                       f"from J_N, FP64, {evals:.3e} evaluations in {dt:.1f} s"}
+
+
+def measured_traffic(workload, kernel_name):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    of this workload, if it was measured on the current sweep source and the
+    same kernel instance; else None."""
+    import re
+    from paper_2104_01284_amd.profiling import sweep_source_hash
+    path = os.path.join(ROOT, "profiles", f"sweep_{PROFILE_NAME.get(workload, workload)}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch=(\S+) sweep_source=(\S+)", text)
+    if not m or m.group(2) != sweep_source_hash() or kernel_name not in text.split("\n")[0]:
+        return None
+    return float(m.group(1))
 
 
 def main():
@@ -188,7 +207,10 @@ def main():
         "V0": V0,
         "V0_all_mean": float(plan.V0.double().mean().cpu()) if batched else V0,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": None if batched else measured_traffic(
+                         args.workload, f"k_sweep_lds<{int(info.sweep_tile)}, {64 * ((int(info.n_t) + 63) // 64)}>"),
+                     "traffic_unit": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "state sweep", "avg_launch_ms": avg_launch_ms, "launches_per_solve": launches,
                      "flops_per_launch": FLOPS_PER_EVAL * evals / max(1, launches)},
     }

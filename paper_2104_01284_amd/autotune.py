@@ -27,16 +27,28 @@ def default_cache_path() -> str:
 def shape_key(inst: dict, device_name: str) -> str:
     n_v, n_s, n_t = (int(inst[g][2]) for g in ("v_grid", "soc_grid", "t_grid"))
     n_u = int(inst["te_grid"][2]) * int(inst["tm_grid"][2])
-    return f"{device_name}|v{n_v}|s{n_s}|t{n_t}|u{n_u}"
+    return f"{device_name}|v{n_v}|s{n_s}|t{n_t}|u{n_u}|N{int(inst['N'])}"
 
 
-def _time_config(inst, kernel, tile, stages, repeats, device):
+def _time_config(inst, kernel, tile, stages, repeats, device, full):
+    """Sweep milliseconds of one configuration: whole solves (full) or the
+    isolated stages `stages` from a zero J_{k+1} (timing does not depend on
+    the values)."""
     import torch
     from .api import Plan
     plan = Plan([inst], timing=True, kernel=kernel, sweep_tile=tile, device=device)
     info = plan.info[0]
     if int(info.sweep_kernel) != kernel or int(info.sweep_tile) != tile:
         return None
+    if full:
+        plan.solve()                                  # warm-up
+        torch.cuda.synchronize(device)
+        plan.sweep_time()
+        for _ in range(repeats):
+            plan.solve()
+        torch.cuda.synchronize(device)
+        ms, _ = plan.sweep_time()
+        return ms / repeats
     Jn = torch.zeros(plan.slab_shape(0), dtype=torch.float32, device=f"cuda:{device}")
     for k in stages:                                  # warm-up
         plan.stage(0, k, Jn)
@@ -46,13 +58,13 @@ def _time_config(inst, kernel, tile, stages, repeats, device):
         for k in stages:
             plan.stage(0, k, Jn)
     torch.cuda.synchronize(device)
-    ms, n = plan.sweep_time()
-    return ms / max(1, n), int(info.soc_shift)
+    ms, _ = plan.sweep_time()
+    return ms / repeats
 
 
-def tune(inst: dict, device: int = 0, repeats: int = 3, candidates=CANDIDATES) -> dict:
-    """Time every candidate on three stages of `inst`; returns the fastest as
-    {"kernel", "tile", "ms", "all": {...}}."""
+def tune(inst: dict, device: int = 0, repeats: int = 2, candidates=CANDIDATES, full: bool = False) -> dict:
+    """Time every candidate on `inst`: its whole solve when `full`, else three
+    of its stages.  Returns the fastest as {"kernel", "tile", "ms", "all"}."""
     N = int(inst["N"])
     stages = sorted({N - 1, N // 2, min(1, N - 1)})
     n_s = int(inst["soc_grid"][2])
@@ -60,9 +72,9 @@ def tune(inst: dict, device: int = 0, repeats: int = 3, candidates=CANDIDATES) -
     for kernel, tile in candidates:
         if tile > n_s and tile > 4:
             continue
-        r = _time_config(inst, kernel, tile, stages, repeats, device)
+        r = _time_config(inst, kernel, tile, stages, repeats, device, full)
         if r is not None:
-            results[f"{kernel}/{tile}"] = r[0]
+            results[f"{kernel}/{tile}"] = r
     if not results:
         return {"kernel": 0, "tile": 0, "ms": None, "all": {}}
     best = min(results, key=results.get)
@@ -70,9 +82,13 @@ def tune(inst: dict, device: int = 0, repeats: int = 3, candidates=CANDIDATES) -
     return {"kernel": kernel, "tile": tile, "ms": results[best], "all": results}
 
 
-def tuned_options(instances, device: int = 0, cache_path: str | None = None, verbose: bool = False):
+def tuned_options(instances, device: int = 0, cache_path: str | None = None, verbose: bool = False,
+                  full: bool | None = None):
     """Per-instance (kernel, tile, split, wg_per_cu) for Plan(inst_opts=...),
-    timing each shape not yet in the cache."""
+    timing each shape not yet in the cache: by whole solves for a single
+    instance (unless `full` is False), by sampled stages for a batch."""
+    if full is None:
+        full = len(instances) == 1
     import torch
     path = cache_path or default_cache_path()
     cache = {}
@@ -87,7 +103,7 @@ def tuned_options(instances, device: int = 0, cache_path: str | None = None, ver
     for inst in instances:
         key = shape_key(inst, name)
         if key not in cache:
-            cache[key] = tune(inst, device)
+            cache[key] = tune(inst, device, full=full)
             dirty = True
             if verbose:
                 print(f"[autotune] {key}: {cache[key]}", file=sys.stderr, flush=True)

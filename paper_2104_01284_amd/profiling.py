@@ -5,9 +5,19 @@
       register and LDS use, launch shape;
   python -m paper_2104_01284_amd.profiling pmc <run_results.db> [kernel-substring]
       per-kernel average of every collected counter (per dispatch).
+  python -m paper_2104_01284_amd.profiling traffic <fetch.db> <write.db> <copy_fetch.db> <copy_write.db>
+                                                   <copy_MiB> <kernel-substring>
+      HBM bytes per dispatch of a kernel from FETCH_SIZE and WRITE_SIZE (KiB
+      per dispatch), each scaled by what the same counter reads for a plain
+      device copy of copy_MiB MiB; prints a summary whose last line is
+      machine-readable.
 """
+import hashlib
+import os
 import sqlite3
 import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def trace(path, title=""):
@@ -45,10 +55,55 @@ def pmc(path, needle=""):
         print(f"{name.split('(')[0][:50]:50s} {cn:28s} dispatches={cnt:6d} avg={avg:16.1f} total={tot:18.1f}")
 
 
+def _counter_rows(path, counter):
+    db = sqlite3.connect(path)
+    tabs = [r[0] for r in db.execute("select name from sqlite_master where type in ('table','view')")]
+    if "counters_collection" in tabs:
+        q = ("select kernel_name, avg(value), count(*) from counters_collection where counter_name = ? "
+             "group by kernel_name")
+    else:
+        q = ("select k.name, avg(p.value), count(*) from pmc_events p join kernels k "
+             "on k.dispatch_id = p.dispatch_id where p.counter_name = ? group by k.name")
+    return db.execute(q, (counter,)).fetchall()
+
+
+def sweep_source_hash():
+    """SHA-256 of the grouped-sweep source; a stored traffic figure is valid
+    only for the kernel it was measured on."""
+    with open(os.path.join(HERE, "csrc", "dp_sweep.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib, needle):
+    copy_kib = float(copy_mib) * 1024.0
+
+    def copy_factor(db, counter):
+        rows = [r for r in _counter_rows(db, counter) if "opy" in r[0] or "elementwise" in r[0]]
+        big = max(rows, key=lambda r: r[1])
+        return copy_kib / big[1], big
+
+    ff, frow = copy_factor(copy_fetch_db, "FETCH_SIZE")
+    fw, wrow = copy_factor(copy_write_db, "WRITE_SIZE")
+    f = [r for r in _counter_rows(fetch_db, "FETCH_SIZE") if needle in r[0]]
+    w = [r for r in _counter_rows(write_db, "WRITE_SIZE") if needle in r[0]]
+    print(f"copy calibration ({copy_mib} MiB): FETCH_SIZE {frow[1]:.1f} KiB -> factor {ff:.3f}; "
+          f"WRITE_SIZE {wrow[1]:.1f} KiB -> factor {fw:.3f}  [{frow[0].split('(')[0][:60]}]")
+    tot = 0.0
+    for (name, fk, n) in f:
+        wk = dict((r[0], r[1]) for r in w).get(name, 0.0)
+        b = (fk * ff + wk * fw) * 1024.0
+        tot = max(tot, b)
+        print(f"{name.split('(')[0][:60]:60s} dispatches={n:5d} FETCH={fk:12.1f} KiB WRITE={wk:12.1f} KiB "
+              f"-> HBM bytes/dispatch {b:.4e}")
+    print(f"traffic_bytes_per_launch={tot:.6e} sweep_source={sweep_source_hash()}")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], " ".join(sys.argv[3:]))
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:8])
     else:
         trace(sys.argv[1])

@@ -9,7 +9,7 @@ def test_cache_times_each_shape_once(tmp_path, monkeypatch):
     import torch
     calls = []
 
-    def fake_tune(inst, device=0, **kw):
+    def fake_tune(inst, device=0, full=False, **kw):
         calls.append(inst["name"])
         return {"kernel": 2, "tile": 8, "ms": 1.0, "all": {"2/8": 1.0}}
 
