@@ -317,41 +317,66 @@ __device__ inline void block_add5(double g[5], double *gacc)
 // gradient terms weighted by rho, and rho times the interpolation weights
 // added to the stage k+1 occupancy.  Wait nodes add rho * tau to dV/dw_t and
 // move in time only.  Nodes without a control keep J_inf and stop the mass.
+// Each workgroup takes a chunk of kAdjChunk consecutive nodes, gathers the
+// ones with rho > 0 into an LDS list (the occupied set is a small part of the
+// grid) and then runs the FP64 work on full waves.
+constexpr int kAdjChunk = 512;
+
 __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
                                                    const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
                                                    const double *__restrict__ rho, double *__restrict__ rho_next,
                                                    double *__restrict__ gacc)
 {
 #pragma clang fp contract(off)
+    __shared__ int s_list[kAdjChunk];
+    __shared__ int s_cnt;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const long S = (long)P.n_v * P.n_s * P.n_t;
-    for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
-        const double r = rho[n];
-        if (!(r > 0.0)) continue;
-        const int m = (int)(n % P.n_t);
-        const long ij = n / P.n_t;
-        const int j = (int)(ij % P.n_s);
-        const int i = (int)(ij / P.n_s);
-        const int u = pik[n];
-        if (u == -2) {
-            const TLEntry e = tl[m];
-            g[3] += r * e.tau;
-            const long base = ((long)i * P.n_s + j) * P.n_t;
-            if (1.0 - e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc], r * (1.0 - e.wf));
-            if (e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc + 1], r * e.wf);
-        } else if (u >= 0) {
-            PT p;
-            double I;
-            Cells x;
-            const double v = P.v_lo + i * P.hv;
-            const double xi = P.s_lo + j * P.hs;
-            if (!successor_cells(P, k, v, xi, (double)j, m, u, p, I, x)) continue;
-            double dc[5], dr[5][3], gJ[3];
-            step_partials(P, v, p, I, dc, dr);
-            interp_grad(P, Jn, x, gJ);
-            for (int q = 0; q < 5; q++) g[q] += r * (dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2]);
-            scatter(P, rho_next, r, x, true);
+    const int lane = threadIdx.x & 63;
+    for (long c0 = blockIdx.x * (long)kAdjChunk; c0 < S; c0 += (long)gridDim.x * kAdjChunk) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < kAdjChunk; j += blockDim.x) {
+            const long n = c0 + j;
+            const bool act = n < S && rho[n] > 0.0;
+            const unsigned long long msk = __ballot(act);
+            int off = 0;
+            if (lane == 0 && msk) off = atomicAdd(&s_cnt, __popcll(msk));
+            off = __shfl(off, 0);
+            if (act) s_list[off + __popcll(msk & ((1ull << lane) - 1ull))] = j;
         }
+        __syncthreads();
+        const int na = s_cnt;
+        for (int a = threadIdx.x; a < na; a += blockDim.x) {
+            const long n = c0 + s_list[a];
+            const double r = rho[n];
+            const int m = (int)(n % P.n_t);
+            const long ij = n / P.n_t;
+            const int j = (int)(ij % P.n_s);
+            const int i = (int)(ij / P.n_s);
+            const int u = pik[n];
+            if (u == -2) {
+                const TLEntry e = tl[m];
+                g[3] += r * e.tau;
+                const long base = ((long)i * P.n_s + j) * P.n_t;
+                if (1.0 - e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc], r * (1.0 - e.wf));
+                if (e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc + 1], r * e.wf);
+            } else if (u >= 0) {
+                PT p;
+                double I;
+                Cells x;
+                const double v = P.v_lo + i * P.hv;
+                const double xi = P.s_lo + j * P.hs;
+                if (!successor_cells(P, k, v, xi, (double)j, m, u, p, I, x)) continue;
+                double dc[5], dr[5][3], gJ[3];
+                step_partials(P, v, p, I, dc, dr);
+                interp_grad(P, Jn, x, gJ);
+                for (int q = 0; q < 5; q++)
+                    g[q] += r * (dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2]);
+                scatter(P, rho_next, r, x, true);
+            }
+        }
+        __syncthreads();   // the list is read before the next chunk rewrites it
     }
     block_add5(g, gacc);
 }
@@ -411,7 +436,9 @@ int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t
                          const double *rho, double *rho_next, double *gacc, hipStream_t s)
 {
     const long S = (long)P.n_v * P.n_s * P.n_t;
-    hipLaunchKernelGGL(k_adj_stage, dim3(grid_for(S)), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
+    long chunks = (S + kAdjChunk - 1) / kAdjChunk;
+    if (chunks > 16384) chunks = 16384;
+    hipLaunchKernelGGL(k_adj_stage, dim3((unsigned)chunks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

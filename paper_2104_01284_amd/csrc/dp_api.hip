@@ -165,6 +165,8 @@ int validate(const dp_problem_desc &d, int b)
     if ((long)d.n_te * d.n_tm > 32767) return fail(DP_EUNSUPPORTED, "instance %d: more than 32767 controls", b);
     if (d.n_v > 32767 || d.n_soc > 32767) return fail(DP_EUNSUPPORTED, "instance %d: grid too large", b);
     if (d.n_t > 1024) return fail(DP_EUNSUPPORTED, "instance %d: n_t > 1024", b);
+    if ((long)d.n_v * d.n_soc * d.n_t > (1L << 30))
+        return fail(DP_EUNSUPPORTED, "instance %d: more than 2^30 states per stage (grid too large)", b);
     if (d.flags & ~DP_WAIT_AT_RED) return fail(DP_EINVAL, "instance %d: unknown flags", b);
     return DP_OK;
 }
