@@ -200,6 +200,8 @@ __device__ inline float shl1(float x)
 
 // Registers per thread that prefetch the next run of control records.
 constexpr int kPrefetch = 4;
+// Rows of a next-stage plane one thread loads per pass when staging.
+constexpr int kStageRows = 8;
 
 // The job and parameter tables come in as separate read-only arguments so
 // that their fields are loaded through the scalar unit.
@@ -358,12 +360,30 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                     sq = 1 - sp;
                 }
                 __syncthreads();
-                for (int rr = 0; rr < nrows; rr++)
-                    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-                        const long g = (long)(wlo + rr) * nt + t;
-                        if (need_p) lds[sp * slot_sz + rr * PITCH + t] = Jn[(long)p * SV + g];
-                        if (need_q) lds[sq * slot_sz + rr * PITCH + t] = Jn[(long)(p + 1) * SV + g];
+                // thread t copies time node t (the block has at least n_t
+                // threads) of kStageRows rows per pass, all loads in flight
+                // before the LDS stores
+                const int t = threadIdx.x;
+                if (t < nt) {
+                    const float *srcp = Jn + (long)p * SV + (long)wlo * nt + t;
+                    const float *srcq = srcp + SV;
+                    for (int r0 = 0; r0 < nrows; r0 += kStageRows) {
+                        float va[kStageRows], vb[kStageRows];
+#pragma unroll
+                        for (int q = 0; q < kStageRows; q++) {
+                            const long off = (long)min(r0 + q, nrows - 1) * nt;
+                            va[q] = need_p ? srcp[off] : 0.0f;
+                            vb[q] = need_q ? srcq[off] : 0.0f;
+                        }
+#pragma unroll
+                        for (int q = 0; q < kStageRows; q++) {
+                            if (r0 + q < nrows) {
+                                if (need_p) lds[sp * slot_sz + (r0 + q) * PITCH + t] = va[q];
+                                if (need_q) lds[sq * slot_sz + (r0 + q) * PITCH + t] = vb[q];
+                            }
+                        }
                     }
+                }
                 plane[sp] = p;
                 plane[sq] = p + 1;
                 SA = sp * slot_sz;
