@@ -44,7 +44,7 @@ struct Inst {
     size_t S = 0;              // slab elements
     std::vector<int> light_of_stage;
     size_t J_off = 0, pi_off = 0, traj_off = 0;
-    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_batj = 0;
+    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_batj = 0, scr_pw = 0;
     int sweep = 0;             // 1 = simple per-node kernel, 2 = grouped LDS kernel
     int jt = 8;                // SoC rows per workgroup of the grouped kernel
     int nsplit = 1;            // largest number of control slices of any of its stages
@@ -345,11 +345,12 @@ static int plan_rounds(dp_plan *p, size_t scr)
             j.nf = (long long)I.scr_nf;
             j.batj = (long long)I.scr_batj;
             j.rec = (long long)I.scr_rec;
+            j.pw = (long long)I.scr_pw;
             if (I.job_of_k.empty()) I.job_of_k.assign(I.N, -1);
             I.job_of_k[k] = (int)p->jobs.size();
             p->jobs.push_back(j);
             R.max_nv = std::max(R.max_nv, I.P.n_v);
-            R.max_records = std::max(R.max_records, (long)I.P.n_v * I.P.n_u * j.ntiles);
+            R.max_records = std::max(R.max_records, (long)I.P.n_v * I.P.n_u * j.ntiles * I.jt);
             R.max_nodes = std::max(R.max_nodes, (long)I.S);
             R.any_split = R.any_split || j.nsplit > 1;
             // a new launch starts where the class changes
@@ -667,6 +668,8 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         scr += align_up(sizeof(int) * d.n_v, 256);
         if (I.sweep == 2) {
             const size_t ntiles = (d.n_soc + I.jt - 1) / I.jt;
+            I.scr_pw = scr;
+            scr += align_up(sizeof(double) * 2 * (size_t)d.n_v * P.n_u, 256);
             I.scr_rec = scr;
             scr += align_up(sizeof(float) * (size_t)d.n_v * ntiles * P.n_u * (12 + 2 * I.jt), 256);
             I.scr_batj = scr;
@@ -945,7 +948,7 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
     B.pik = pi_out;
     int *q = queue_slot(p, scratch, p->n_q_slots - 1);
     if (launch_fill_i32(q, 8, 0, s)) return hip_fail(hipGetLastError(), "queue reset launch");
-    if (launch_stage_jobs(B, 1, I.P.n_v, (long)I.P.n_v * I.P.n_u * j.ntiles, s))
+    if (launch_stage_jobs(B, 1, I.P.n_v, (long)I.P.n_v * I.P.n_u * j.ntiles * I.jt, s))
         return hip_fail(hipGetLastError(), "stage table launch");
     int rc = time_begin(p, s);
     if (rc) return rc;

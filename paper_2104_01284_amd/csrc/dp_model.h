@@ -92,6 +92,7 @@ struct StageJob {
     int pad;
     long long jn, jk, pik;                 // J_{k+1}, J_k (J buffer), pi_k (pi buffer)
     long long st, nf, batj, rec, pv, pu;   // stage data and partial results (scratch)
+    long long pw;                          // battery power and time step per sorted control (scratch)
 };
 
 // Launch-wide pointers of a set of jobs.  Jn / Jk / pik, when set, replace the

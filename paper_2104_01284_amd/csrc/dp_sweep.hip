@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
     const int i = blockIdx.x;
     if (i >= P.n_v) return;
     SortedEntry *__restrict__ out = (SortedEntry *)(B.scr + jb.st);
+    double2 *__restrict__ pw = (double2 *)(B.scr + jb.pw);
     int *__restrict__ nfeas = (int *)(B.scr + jb.nf);
     const int u = threadIdx.x;
     const int nu = P.n_u;
@@ -46,6 +47,7 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
     for (int q = threadIdx.x; q < kSortBins; q += blockDim.x) s_hist[q] = 0;
     __syncthreads();
     SortedEntry e;
+    double2 pbdt = make_double2(0.0, 0.0);   // battery power and time step, for the battery records
     int iv = -1;
     if (u < nu) {
 #pragma clang fp contract(off)
@@ -75,6 +77,7 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
         e.iv = c;
         e.dtc = dtc;
         e.u = u;
+        pbdt = make_double2(p.Pb, p.dt);
         if (ok) iv = c;
     }
     if (iv >= 0) {
@@ -121,6 +124,7 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
             if (iv >= 0) {
                 const int pos = s_hist[iv - base] + rank;
                 out[(long)i * nu + pos] = e;
+                pw[(long)i * nu + pos] = pbdt;
                 if (rank == cnt - 1) s_hist[iv - base] += cnt;
             }
         }
@@ -132,62 +136,67 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
 // u), the tile header, padding, then the tile's (fx, gx) pairs.
 __host__ __device__ constexpr int rec_words(int JT) { return 12 + 2 * JT; }
 
-// Battery coordinates of one (speed node, sorted position, SoC tile), written
+// Battery coordinates of one (speed node, SoC tile, sorted position), written
 // as one packed record per (speed node, tile, position) so that the sweep
 // stages a run of controls with one contiguous copy: per SoC node the lower
 // cell (also kept in batj for the general path) and the weights (fx, gx);
 // the header is the first node's cell when the tile's cells are consecutive
-// (jx0 + q), else -1.
-__global__ void k_stage_bat_sorted(StageBase B)
+// (jx0 + q), else -1.  One lane per (record, SoC row): the JT lanes of a
+// record are consecutive and aligned (JT divides the wave), consecutive
+// records are consecutive in memory, and the battery power and time step of
+// the control come from the sort (no second powertrain evaluation).
+__global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
 {
 #pragma clang fp contract(off)
     const StageJob &jb = B.jobs[blockIdx.y];
     const DevInst &P = B.insts[jb.inst];
-    const int k = jb.k, JT = jb.jt, ntiles = jb.ntiles;
+    const int JT = jb.jt, ntiles = jb.ntiles;
     const SortedEntry *__restrict__ st = (const SortedEntry *)(B.scr + jb.st);
+    const double2 *__restrict__ pw = (const double2 *)(B.scr + jb.pw);
     const int *__restrict__ nfeas = (const int *)(B.scr + jb.nf);
     int *__restrict__ batj = (int *)(B.scr + jb.batj);
     float *__restrict__ rec = (float *)(B.scr + jb.rec);
     const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const long total = (long)P.n_v * P.n_u * ntiles;
-    if (idx >= total) return;
-    const int tile = (int)(idx % ntiles);
-    const long ir = idx / ntiles;
-    const int r = (int)(ir % P.n_u);
-    const int i = (int)(ir / P.n_u);
-    if (r >= nfeas[i]) return;
-    const SortedEntry e = st[ir];
-    const int u = e.u;
-    const double v = P.v_lo + i * P.hv;
-    const PT p = powertrain(P, k, v, u / P.n_m, u % P.n_m);
+    const long total = (long)P.n_v * ntiles * P.n_u * JT;
+    if (idx >= total) return;          // whole records: total is a multiple of JT
+    const int q = (int)(idx % JT);
+    const long t2 = idx / JT;
+    const int r = (int)(t2 % P.n_u);
+    const long t3 = t2 / P.n_u;
+    const int tile = (int)(t3 % ntiles);
+    const int i = (int)(t3 / ntiles);
+    if (r >= nfeas[i]) return;         // the same for the JT lanes of the record
+    const long ir = (long)i * P.n_u + r;
     const int j0 = tile * JT;
     const int jc = min(JT, P.n_s - j0);
+    int jx = -1;
+    double fx = 0.0;
+    if (q < jc) {
+        const int j = j0 + q;
+        const double2 pd = pw[ir];
+        double I;
+        const double xi = P.s_lo + j * P.hs;
+        if (battery_current(P, pd.x, xi, I)) {
+            const double rs = (double)j - (pd.y * I) / (P.Cnom * P.hs);
+            if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
+        }
+        batj[ir * P.n_s + j] = jx;
+    }
+    // consecutive cells across the record's rows q < jc
+    const int lane = threadIdx.x & 63;
+    const int base = lane & ~(JT - 1);
+    const int jx0 = __shfl(jx, base);
+    const bool ok = q >= jc || (jx >= 0 && jx == jx0 + q);
+    const unsigned long long bad = __ballot(!ok);
+    const unsigned long long grp = (JT == 64 ? ~0ull : ((1ull << JT) - 1ull)) << base;
+    const bool regular = (bad & grp) == 0;
     const int CW = rec_words(JT);
     float *out = rec + (((long)i * ntiles + tile) * P.n_u + r) * CW;
-    int jx0 = -1;
-    bool regular = true;
-    for (int q = 0; q < JT; q++) {
-        int jx = -1;
-        double fx = 0.0;
-        if (q < jc) {
-            const int j = j0 + q;
-            double I;
-            const double xi = P.s_lo + j * P.hs;
-            if (battery_current(P, p.Pb, xi, I)) {
-                const double rs = (double)j - (p.dt * I) / (P.Cnom * P.hs);
-                if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
-            }
-            batj[ir * P.n_s + j] = jx;
-            if (q == 0) jx0 = jx;
-            regular = regular && jx >= 0 && jx == jx0 + q;
-        }
-        out[12 + 2 * q] = jx >= 0 ? (float)fx : 0.0f;
-        out[13 + 2 * q] = jx >= 0 ? (float)(1.0 - fx) : 0.0f;
-    }
-    const float *ef = reinterpret_cast<const float *>(&e);
-    for (int w = 0; w < 8; w++) out[w] = ef[w];
-    out[8] = __int_as_float(regular ? jx0 : -1);
-    out[9] = out[10] = out[11] = 0.0f;
+    out[12 + 2 * q] = jx >= 0 ? (float)fx : 0.0f;
+    out[13 + 2 * q] = jx >= 0 ? (float)(1.0 - fx) : 0.0f;
+    const float *ef = reinterpret_cast<const float *>(&st[ir]);
+    for (int w = q; w < 12; w += JT)
+        out[w] = w < 8 ? ef[w] : (w == 8 ? __int_as_float(regular ? jx0 : -1) : 0.0f);
 }
 
 // ------------------------------------------------------------------ sweep --
@@ -548,6 +557,7 @@ int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_record
     hipLaunchKernelGGL(k_stage_sort, dim3(max_nv, njobs), dim3(1024), 0, s, B);
     if (hipGetLastError() != hipSuccess) return -1;
     hipLaunchKernelGGL(k_stage_bat_sorted, dim3((unsigned)((max_records + 255) / 256), njobs), dim3(256), 0, s, B);
+    // (max_records counts record lanes: records x SoC rows per record)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
