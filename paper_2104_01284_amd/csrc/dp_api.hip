@@ -287,7 +287,10 @@ static int plan_rounds(dp_plan *p, size_t scr)
     p->rounds.assign(maxN, Round{});
     std::vector<int> ib;
     int q_slot = 0;
-    const long target = 8L * p->n_cu;
+    // about 32 items per CU (six or more per resident workgroup), so that
+    // the last items of a launch are short against the whole; a slice costs
+    // a partial-result store and a share of the combine
+    const long target = 32L * p->n_cu;
     for (int r = 0; r < maxN; r++) {
         Round &R = p->rounds[r];
         long base = 0;
@@ -310,8 +313,8 @@ static int plan_rounds(dp_plan *p, size_t scr)
             int ns = I.split_opt > 0 ? I.split_opt : ns_round;
             ns = std::max(1, std::min(ns, std::min(16, I.P.n_u)));
             I.nsplit = std::max(I.nsplit, ns);
-            const int pitch = ((I.P.n_t + 63) / 64) * 64;
-            const int threads = 64 * ((I.P.n_t + 62) / 63);
+            const int pitch = sweep_pitch(I.P.n_t);
+            const int threads = sweep_threads(I.P.n_t);
             t.push_back({b, I.jt, pitch, threads, ns, (double)I.P.n_u / ns});
         }
         std::stable_sort(t.begin(), t.end(), [](const Tmp &x, const Tmp &y) {
@@ -333,7 +336,7 @@ static int plan_rounds(dp_plan *p, size_t scr)
             j.ntiles = (I.P.n_s + I.jt - 1) / I.jt;
             j.nsplit = t[q].ns;
             j.H = I.H;
-            j.rw = I.jt + 2 * I.H + 2;
+            j.rw = sweep_rows(I.jt, I.H);
             j.nitems = I.P.n_v * j.ntiles * j.nsplit;
             const int L = I.light_of_stage[k];
             j.tl = L >= 0 ? (int)(I.tl_dev_off + (size_t)L * I.P.n_t) : -1;
@@ -608,9 +611,10 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         // state-sweep variant: the grouped LDS kernel when its tables and
         // staged planes fit, else the simple per-node kernel
         I.H = soc_shift_bound(P, d);
-        // SoC rows per workgroup: the largest tile that still leaves about
-        // three resident waves per SIMD (LDS of one CU is shared by its
-        // workgroups); a caller tile overrides
+        // SoC rows per workgroup: the largest tile that still leaves three
+        // and a half resident waves per SIMD (LDS of one CU is shared by its
+        // workgroups; the sweep waits on LDS and barriers, so resident waves
+        // matter more than the per-tile saving); a caller tile overrides
         const size_t lds_cu = (size_t)p->lds_per_cu;
         const int waves = (d.n_t + 62) / 63;
         auto waves_per_simd = [&](int t) {
@@ -634,7 +638,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             for (int t : cand) {
                 if (t > 4 && d.n_soc < t) continue;
                 const double w = waves_per_simd(t);
-                if (w >= 2.75) {
+                if (w >= 3.5) {
                     jt = t;
                     break;
                 }
@@ -952,7 +956,7 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
         return hip_fail(hipGetLastError(), "stage table launch");
     int rc = time_begin(p, s);
     if (rc) return rc;
-    const int pitch = ((I.P.n_t + 63) / 64) * 64, threads = 64 * ((I.P.n_t + 62) / 63);
+    const int pitch = sweep_pitch(I.P.n_t), threads = sweep_threads(I.P.n_t);
     if (launch_sweep_jobs(I.jt, pitch, threads, B, 1, nullptr, j.nitems, q, I.grid,
                           lds_sweep_bytes(I.jt, I.H, I.P.n_t), s))
         return hip_fail(hipGetLastError(), "sweep launch");

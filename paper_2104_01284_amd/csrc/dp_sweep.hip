@@ -563,9 +563,8 @@ int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_record
 
 size_t lds_sweep_bytes(int JT, int H, int n_t)
 {
-    const int pitch = ((n_t + 63) / 64) * 64;
-    const int threads = 64 * ((n_t + 62) / 63);
-    return sizeof(float) * (2 * (size_t)(JT + 2 * H + 2) * pitch + (size_t)kPrefetch * threads);
+    return sizeof(float) * (2 * (size_t)sweep_rows(JT, H) * sweep_pitch(n_t) +
+                            (size_t)kPrefetch * sweep_threads(n_t));
 }
 
 size_t lds_job_index_bytes(int njobs) { return njobs > 1 ? sizeof(int) * (size_t)(((njobs + 64) / 64) * 64) : 0; }
@@ -580,21 +579,37 @@ static int launch_sweep_p(int pitch, dim3 grid, dim3 block, size_t lds, hipStrea
         hipLaunchKernelGGL((k_sweep_lds<JT, X>), grid, block, lds, s, B, B.jobs, B.insts, njobs, item_begin, total, \
                            queue);                                                                              \
         return hipGetLastError() == hipSuccess ? 0 : -1;
+        ECODP_PITCH(32)
         ECODP_PITCH(64)
+        ECODP_PITCH(96)
         ECODP_PITCH(128)
+        ECODP_PITCH(160)
         ECODP_PITCH(192)
+        ECODP_PITCH(224)
         ECODP_PITCH(256)
+        ECODP_PITCH(288)
         ECODP_PITCH(320)
+        ECODP_PITCH(352)
         ECODP_PITCH(384)
+        ECODP_PITCH(416)
         ECODP_PITCH(448)
+        ECODP_PITCH(480)
         ECODP_PITCH(512)
+        ECODP_PITCH(544)
         ECODP_PITCH(576)
+        ECODP_PITCH(608)
         ECODP_PITCH(640)
+        ECODP_PITCH(672)
         ECODP_PITCH(704)
+        ECODP_PITCH(736)
         ECODP_PITCH(768)
+        ECODP_PITCH(800)
         ECODP_PITCH(832)
+        ECODP_PITCH(864)
         ECODP_PITCH(896)
+        ECODP_PITCH(928)
         ECODP_PITCH(960)
+        ECODP_PITCH(992)
         ECODP_PITCH(1024)
 #undef ECODP_PITCH
     default: return -2;
