@@ -13,11 +13,12 @@ int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *p
                  const BatEntry *bat, const TLEntry *tl, hipStream_t s);
 int launch_root(const DevInst &P, const float *J1, float *V0, int16_t *u0, hipStream_t s);
 
-// Grouped sweep geometry: floats per staged plane row (time nodes rounded up
-// to 32, so that the rows of a small grid do not waste LDS), staged SoC rows
+// Grouped sweep geometry: floats per staged plane row (time nodes plus at
+// least one padding column, rounded up to 32 so that the rows of a small grid
+// do not waste LDS), staged SoC rows
 // of a tile of JT rows whose successor cells move by at most H, and threads
 // per workgroup (a wave covers 63 time nodes plus the neighbour of the last).
-inline int sweep_pitch(int n_t) { return ((n_t + 31) / 32) * 32; }
+inline int sweep_pitch(int n_t) { return ((n_t + 1 + 31) / 32) * 32; }
 inline int sweep_rows(int JT, int H) { return JT + 2 * H + 1; }
 inline int sweep_threads(int n_t) { return 64 * ((n_t + 62) / 63); }
 

@@ -211,6 +211,9 @@ __device__ inline float shl1(float x)
 constexpr int kPrefetch = 4;
 // Rows of a next-stage plane one thread loads per pass when staging.
 constexpr int kStageRows = 8;
+// Value of the staged columns past the last time node (half the largest
+// float, so that sums of two of them stay finite).
+constexpr float kPad = 1.7014118e38f;
 
 // The job and parameter tables come in as separate read-only arguments so
 // that their fields are loaded through the scalar unit.
@@ -373,6 +376,17 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                 // threads) of kStageRows rows per pass, all loads in flight
                 // before the LDS stores
                 const int t = threadIdx.x;
+                if (t >= nt && t < PITCH) {
+                    // columns past the last time node hold a huge finite value:
+                    // a candidate whose successor time leaves the grid (or sits
+                    // on the last node with a positive fraction) is then far
+                    // above J_inf, while 0 x huge stays exact for a zero
+                    // fraction on the last node
+                    for (int rr = 0; rr < nrows; rr++) {
+                        if (need_p) lds[sp * slot_sz + rr * PITCH + t] = kPad;
+                        if (need_q) lds[sq * slot_sz + rr * PITCH + t] = kPad;
+                    }
+                }
                 if (t < nt) {
                     const float *srcp = Jn + (long)p * SV + (long)wlo * nt + t;
                     const float *srcq = srcp + SV;
@@ -405,15 +419,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             const int u = __float_as_int(ce[7]);
             const int jx0 = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
             const int pos = m + dtc;
-            const bool okt = out_lane && (pos < nt - 1 || (pos == nt - 1 && ft == 0.0f));
-            const int posc = min(pos, nt - 1);
-            // lanes whose successor time is off the grid get an infinite stage
-            // cost, so their candidates never win
-            const float c = okt ? c0f : __builtin_inff();
             const bool regular = jx0 >= wlo && jx0 + jc <= whi;
             const float *wp = ce + 12;
             float Qv[JT];
             if (regular && jc == JT) {
+                // successor times past the grid read the padding columns
+                const int posc = min(pos, PITCH - 1);
+                const float c = c0f;
                 const int a0 = SA + (jx0 - wlo) * PITCH + posc;
                 const int b0 = SB + (jx0 - wlo) * PITCH + posc;
                 // speed lerp on the JT+1 SoC rows, then the time lerp with the
@@ -427,6 +439,11 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
 #pragma unroll
                 for (int q = 0; q < JT; q++) Qv[q] = fmaf(wp[2 * q], T[q + 1], fmaf(wp[2 * q + 1], T[q], c));
             } else {
+                const bool okt = out_lane && (pos < nt - 1 || (pos == nt - 1 && ft == 0.0f));
+                const int posc = min(pos, nt - 1);
+                // lanes whose successor time is off the grid get an infinite
+                // stage cost, so their candidates never win
+                const float c = okt ? c0f : __builtin_inff();
                 const int r = c0 + cr;
 #pragma unroll
                 for (int q = 0; q < JT; q++) {
