@@ -125,7 +125,9 @@ def main():
     print(f"[bench] workload {DESCR[args.workload]}", file=sys.stderr, flush=True)
     opts = dict(sweep_tile=args.tile, split=args.split, wg_per_cu=args.wg_per_cu, kernel=args.kernel)
     tuned = None
-    if not args.no_tune and not (args.kernel or args.tile):
+    # a batch keeps the library's per-instance choice: the tuner times shapes
+    # alone, while in a batch they share the GPU with the other instances
+    if not args.no_tune and not (args.kernel or args.tile) and not batched:
         from paper_2104_01284_amd.autotune import tuned_options
         t0 = time.perf_counter()
         tuned = tuned_options(insts, verbose=True)

@@ -611,18 +611,25 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         // state-sweep variant: the grouped LDS kernel when its tables and
         // staged planes fit, else the simple per-node kernel
         I.H = soc_shift_bound(P, d);
-        // SoC rows per workgroup: the largest tile that still leaves three
-        // and a half resident waves per SIMD (LDS of one CU is shared by its
-        // workgroups; the sweep waits on LDS and barriers, so resident waves
-        // matter more than the per-tile saving); a caller tile overrides
+        // SoC rows per workgroup: the largest tile that still leaves five
+        // resident waves per SIMD (the sweep waits on LDS and barriers, so
+        // resident waves matter more than the per-tile saving), six in a
+        // batch, where the launches of a round share the CUs; else the tile
+        // with the most; a caller tile overrides
+        const double min_waves = n_inst > 1 ? 6.0 : 5.0;
         const size_t lds_cu = (size_t)p->lds_per_cu;
         const int waves = (d.n_t + 62) / 63;
+        // resident waves per SIMD of the grouped sweep with tile t: bounded by
+        // the LDS of a CU, by 8 waves per SIMD and by the kernel's registers
+        // (512 per SIMD lane, allocated in granules of 8)
         auto waves_per_simd = [&](int t) {
             const size_t bytes = lds_sweep_bytes(t, I.H, d.n_t);
             if (bytes > lds_cu) return 0.0;
             size_t wg = lds_cu / bytes;
             if (wg * waves > 32) wg = 32 / waves;
-            return (double)(wg * waves) / 4.0;
+            const int vg = (sweep_vgprs(t, sweep_pitch(d.n_t)) + 7) / 8 * 8;
+            const double w = (double)(wg * waves) / 4.0;
+            return std::min(w, (double)(512 / vg));
         };
         int jt = 0;
         const int32_t *io = p->opt.inst_opt ? p->opt.inst_opt + 4 * b : nullptr;
@@ -638,7 +645,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             for (int t : cand) {
                 if (t > 4 && d.n_soc < t) continue;
                 const double w = waves_per_simd(t);
-                if (w >= 3.5) {
+                if (w >= min_waves) {
                     jt = t;
                     break;
                 }

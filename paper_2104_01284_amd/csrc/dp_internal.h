@@ -26,6 +26,7 @@ inline int sweep_threads(int n_t) { return 64 * ((n_t + 62) / 63); }
 int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_records, hipStream_t s);
 size_t lds_sweep_bytes(int JT, int H, int n_t);
 size_t lds_job_index_bytes(int njobs);
+int sweep_vgprs(int JT, int pitch);
 int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int njobs, const int *item_begin,
                       int total, int *queue, int grid, size_t lds, hipStream_t s);
 int launch_combine_jobs(const StageBase &B, int njobs, long max_nodes, hipStream_t s);

@@ -633,6 +633,65 @@ static int launch_sweep_p(int pitch, dim3 grid, dim3 block, size_t lds, hipStrea
     }
 }
 
+// Vector registers per lane of the grouped-sweep kernel instance (queried
+// from the loaded code object; a conservative estimate if the query fails).
+template <int JT>
+static int sweep_vgprs_p(int pitch)
+{
+    hipFuncAttributes a;
+    hipError_t e = hipErrorInvalidValue;
+    switch (pitch) {
+#define ECODP_PITCH(X)                                                                  \
+    case X:                                                                             \
+        e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_sweep_lds<JT, X>)); \
+        break;
+        ECODP_PITCH(32)
+        ECODP_PITCH(64)
+        ECODP_PITCH(96)
+        ECODP_PITCH(128)
+        ECODP_PITCH(160)
+        ECODP_PITCH(192)
+        ECODP_PITCH(224)
+        ECODP_PITCH(256)
+        ECODP_PITCH(288)
+        ECODP_PITCH(320)
+        ECODP_PITCH(352)
+        ECODP_PITCH(384)
+        ECODP_PITCH(416)
+        ECODP_PITCH(448)
+        ECODP_PITCH(480)
+        ECODP_PITCH(512)
+        ECODP_PITCH(544)
+        ECODP_PITCH(576)
+        ECODP_PITCH(608)
+        ECODP_PITCH(640)
+        ECODP_PITCH(672)
+        ECODP_PITCH(704)
+        ECODP_PITCH(736)
+        ECODP_PITCH(768)
+        ECODP_PITCH(800)
+        ECODP_PITCH(832)
+        ECODP_PITCH(864)
+        ECODP_PITCH(896)
+        ECODP_PITCH(928)
+        ECODP_PITCH(960)
+        ECODP_PITCH(992)
+        ECODP_PITCH(1024)
+#undef ECODP_PITCH
+    default: break;
+    }
+    if (e == hipSuccess && a.numRegs > 0) return a.numRegs;
+    (void)hipGetLastError();
+    return JT == 16 ? 128 : (JT == 8 ? 96 : 80);
+}
+
+int sweep_vgprs(int JT, int pitch)
+{
+    if (JT == 16) return sweep_vgprs_p<16>(pitch);
+    if (JT == 8) return sweep_vgprs_p<8>(pitch);
+    return sweep_vgprs_p<4>(pitch);
+}
+
 int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int njobs, const int *item_begin,
                       int total, int *queue, int grid, size_t lds, hipStream_t s)
 {
