@@ -31,9 +31,9 @@ def shape_key(inst: dict, device_name: str) -> str:
 
 
 def _time_config(inst, kernel, tile, stages, repeats, device, full):
-    """Sweep milliseconds of one configuration: whole solves (full) or the
-    isolated stages `stages` from a zero J_{k+1} (timing does not depend on
-    the values)."""
+    """Milliseconds of one configuration: a whole solve (full) or the sweep
+    launches of the isolated stages `stages` from a zero J_{k+1} (timing does
+    not depend on the values)."""
     import torch
     from .api import Plan
     plan = Plan([inst], timing=True, kernel=kernel, sweep_tile=tile, device=device)
@@ -41,14 +41,18 @@ def _time_config(inst, kernel, tile, stages, repeats, device, full):
     if int(info.sweep_kernel) != kernel or int(info.sweep_tile) != tile:
         return None
     if full:
+        # whole solves: the stage tables of the next round run beside the
+        # sweep, so the solve time (not the sweep launches alone) decides
         plan.solve()                                  # warm-up
         torch.cuda.synchronize(device)
-        plan.sweep_time()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
         for _ in range(repeats):
             plan.solve()
+        b.record()
         torch.cuda.synchronize(device)
-        ms, _ = plan.sweep_time()
-        return ms / repeats
+        return a.elapsed_time(b) / repeats
     Jn = torch.zeros(plan.slab_shape(0), dtype=torch.float32, device=f"cuda:{device}")
     for k in stages:                                  # warm-up
         plan.stage(0, k, Jn)

@@ -51,6 +51,7 @@ struct Inst {
     int split_opt = 0;         // caller's control slices (0 = chosen per round)
     int wg_opt = 0;            // caller's resident sweep workgroups per CU (0 = by LDS)
     size_t scr_pv = 0, scr_pu = 0, scr_rec = 0;
+    size_t tab_stride = 0;     // bytes from the first stage-table set to the second (grouped sweep)
     int grid = 0;              // persistent workgroups of a grouped sweep of this instance alone
     int H = 0;                 // bound on the SoC-cell shift of one step
     size_t tl_dev_off = 0;     // offset (entries) of this instance's TL table in the plan's TL array
@@ -106,6 +107,9 @@ struct dp_plan {
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[kSide] = {nullptr, nullptr, nullptr};
+    // the stage tables of the next round are built on this stream
+    hipStream_t tstream = nullptr;
+    hipEvent_t tfork = nullptr, tjoin = nullptr;
     // DP_GRAPH: the captured solve and the buffers it was captured with
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -344,11 +348,12 @@ static int plan_rounds(dp_plan *p, size_t scr)
             j.jn = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k + 1 : ((k + 1) & 1)));
             j.jk = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k : (k & 1)));
             j.pik = (long long)(I.pi_off + sizeof(int16_t) * I.S * (size_t)k);
-            j.st = (long long)I.scr_st;
-            j.nf = (long long)I.scr_nf;
-            j.batj = (long long)I.scr_batj;
-            j.rec = (long long)I.scr_rec;
-            j.pw = (long long)I.scr_pw;
+            const long long set = (long long)((r & 1) * I.tab_stride);   // table set of this round
+            j.st = (long long)I.scr_st + set;
+            j.nf = (long long)I.scr_nf + set;
+            j.batj = (long long)I.scr_batj + set;
+            j.rec = (long long)I.scr_rec + set;
+            j.pw = (long long)I.scr_pw + set;
             if (I.job_of_k.empty()) I.job_of_k.assign(I.N, -1);
             I.job_of_k[k] = (int)p->jobs.size();
             p->jobs.push_back(j);
@@ -673,6 +678,9 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             if (wg < 1) wg = 1;
             I.grid = (int)(wg * (size_t)p->n_cu);
         }
+        // stage tables; the grouped sweep keeps two sets, so that the tables
+        // of the next round are built while this round's sweep runs
+        const size_t tab0 = scr;
         I.scr_st = scr;
         scr += align_up(sizeof(SortedEntry) * d.n_v * P.n_u, 256);
         I.scr_nf = scr;
@@ -685,6 +693,8 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             scr += align_up(sizeof(float) * (size_t)d.n_v * ntiles * P.n_u * (12 + 2 * I.jt), 256);
             I.scr_batj = scr;
             scr += align_up(sizeof(int) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
+            I.tab_stride = scr - tab0;
+            scr += I.tab_stride;
         } else {
             I.scr_bat = scr;
             scr += align_up(sizeof(BatEntry) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
@@ -709,6 +719,15 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
             dp_destroy(p);
             return hip_fail(e, "capture stream");
+        }
+    }
+    if (p->rounds.size() > 1) {
+        e = hipStreamCreateWithFlags(&p->tstream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->tfork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->tjoin, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            dp_destroy(p);
+            return hip_fail(e, "table stream");
         }
     }
     bool multi = false;
@@ -833,6 +852,7 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
     if (launch_fill_i32(queue_slot(p, scratch, 0), 8L * p->n_q_slots, 0, s))
         return hip_fail(hipGetLastError(), "queue reset launch");
     const StageBase base = stage_base(p, J, pi, scratch);
+    bool pre = false;   // this round's grouped-sweep tables were launched on the table stream
     for (size_t r = 0; r < p->rounds.size(); r++) {
         const Round &R = p->rounds[r];
         for (int b : R.simple) {
@@ -845,8 +865,28 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
         if (R.njobs == 0) continue;
         StageBase B = base;
         B.jobs = p->dev_jobs + R.job_begin;
-        if (launch_stage_jobs(B, R.njobs, R.max_nv, R.max_records, s))
+        if (pre) {
+            hipError_t e = hipStreamWaitEvent(s, p->tjoin, 0);
+            if (e != hipSuccess) return hip_fail(e, "table join");
+        } else if (launch_stage_jobs(B, R.njobs, R.max_nv, R.max_records, s)) {
             return hip_fail(hipGetLastError(), "stage table launch");
+        }
+        // the next round's tables (the other table set, last read by the
+        // previous round, which is already ordered before this point) are
+        // built beside this round's sweep
+        pre = false;
+        if (p->tstream && r + 1 < p->rounds.size() && p->rounds[r + 1].njobs > 0) {
+            const Round &R1 = p->rounds[r + 1];
+            StageBase B1 = base;
+            B1.jobs = p->dev_jobs + R1.job_begin;
+            hipError_t e = hipEventRecord(p->tfork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(p->tstream, p->tfork, 0);
+            if (e != hipSuccess) return hip_fail(e, "table fork");
+            if (launch_stage_jobs(B1, R1.njobs, R1.max_nv, R1.max_records, p->tstream))
+                return hip_fail(hipGetLastError(), "stage table launch");
+            if ((e = hipEventRecord(p->tjoin, p->tstream)) != hipSuccess) return hip_fail(e, "table join");
+            pre = true;
+        }
         // launches of different kernel classes are independent: without
         // DP_TIMING they run side by side on the plan's streams, so one
         // launch's tail overlaps the next one's start
@@ -1056,6 +1096,9 @@ void dp_destroy(dp_plan *p)
         if (p->join[q]) (void)hipEventDestroy(p->join[q]);
     }
     if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->tstream) (void)hipStreamDestroy(p->tstream);
+    if (p->tfork) (void)hipEventDestroy(p->tfork);
+    if (p->tjoin) (void)hipEventDestroy(p->tjoin);
     if (p->dev_tables) (void)hipFree(p->dev_tables);
     if (p->dev_params) (void)hipFree(p->dev_params);
     delete p;
