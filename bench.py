@@ -81,8 +81,9 @@ def measured_traffic(workload, kernel_name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default per workload: plain 1000, paper 200, realistic 50, batched 10, large 5)")
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="realistic", choices=sorted(DESCR))
     ap.add_argument("--tile", type=int, default=0, help="SoC rows per sweep workgroup (4, 8, 16; 0 automatic)")
     ap.add_argument("--split", type=int, default=0, help="control slices per node tile (0 automatic)")
@@ -95,6 +96,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"plain": 1000, "paper": 200, "realistic": 50, "batched": 10, "large": 5}[args.workload]
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
               f"run with --gpus 1", file=sys.stderr)
@@ -163,7 +166,7 @@ def main():
         plan.sweep_time()                   # discard warm-up sweep events
 
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for q in range(args.steps):
@@ -172,14 +175,22 @@ def main():
         ev[q][1].record(stream)
         if not batched:
             plan.rollout()
+            ev[q][2].record(stream)
             plan.adjoint()
+            ev[q][3].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if not batched:
         sweep_ms, launches = plan.sweep_time()
         sweep_ms /= args.steps
         launches //= args.steps
-    solve_ms = [a.elapsed_time(b) for a, b in ev]
+    solve_ms = [e[0].elapsed_time(e[1]) for e in ev]
+    parts = {}
+    if not batched:
+        roll = [e[1].elapsed_time(e[2]) for e in ev]
+        adj = [e[2].elapsed_time(e[3]) for e in ev]
+        parts = {"rollout_ms": statistics.mean(roll), "rollout_us_per_stage": 1e3 * statistics.mean(roll) / inst["N"],
+                 "adjoint_ms": statistics.mean(adj), "adjoint_us_per_stage": 1e3 * statistics.mean(adj) / inst["N"]}
     ms_per_step = wall * 1e3 / args.steps
     V0 = float(plan.V0.cpu()[0])
 
@@ -206,6 +217,7 @@ def main():
                      "var": statistics.pvariance(solve_ms) if len(solve_ms) > 1 else 0.0,
                      "max": max(solve_ms), "median": statistics.median(solve_ms)},
         "solve_evals_per_s": evals / (statistics.mean(solve_ms) * 1e-3),
+        **parts,
         "V0": V0,
         "V0_all_mean": float(plan.V0.double().mean().cpu()) if batched else V0,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -249,3 +249,41 @@ def test_realistic_sampled_isolated_stages(torch):
             assert abs(Jg[i, j, m] - Jo) <= REL_J * max(1.0, abs(Jo)), (k, i, j, m, Jg[i, j, m], Jo)
             if pg[i, j, m] != po:
                 assert q2 - Jo < REL_GAP * max(1.0, abs(Jo)), (k, i, j, m, pg[i, j, m], po, q2 - Jo)
+
+
+def test_large_last_stages_and_sampled_isolated(torch):
+    """The 3 km instance (300 stages, 201x81x401 states) in the benchmark's
+    launch configuration: the last five stages on the full grid against the
+    oracle's own recursion from J_N, and sampled nodes of stages 0, 150 and
+    298 against the oracle fed the GPU's J_{k+1}."""
+    inst = ins.large()
+    N = inst["N"]
+    plan = Plan([inst], store_all=True)
+    say("large_3km full solve")
+    plan.solve()
+    torch.cuda.synchronize()
+    I = oracle.Instance(inst)
+    Jo = oracle.terminal(I)
+    JN = plan.values(0)[N].cpu().numpy().astype(np.float64)
+    assert np.array_equal(JN, Jo.reshape(JN.shape).astype(np.float32).astype(np.float64))
+    for k in range(N - 1, N - 6, -1):
+        say("large_3km full-grid stage", k)
+        Jo, _, _ = oracle.stage(I, k, Jo)
+        Jg = plan.values(0)[k].cpu().numpy().astype(np.float64)
+        Jo_ = Jo.reshape(Jg.shape)
+        err = np.abs(Jg - Jo_) / np.maximum(1.0, np.abs(Jo_))
+        say("max relative J error", float(err.max()))
+        assert err.max() < 1e-4, (k, float(err.max()))
+    rng = np.random.default_rng(5)
+    shp = plan.slab_shape(0)
+    for k in (0, 150, 298):
+        say("large_3km sampled isolated stage", k)
+        Jn = plan.values(0)[k + 1].cpu().numpy().astype(np.float64).ravel()
+        Jg = plan.values(0)[k].cpu().numpy().astype(np.float64)
+        pg = plan.policy(0, k).cpu().numpy()
+        for _ in range(150):
+            i, j, m = (int(rng.integers(0, n)) for n in shp)
+            Jo_n, po, q2 = oracle.node(I, k, Jn, i, j, m)
+            assert abs(Jg[i, j, m] - Jo_n) <= REL_J * max(1.0, abs(Jo_n)), (k, i, j, m, Jg[i, j, m], Jo_n)
+            if pg[i, j, m] != po:
+                assert q2 - Jo_n < REL_GAP * max(1.0, abs(Jo_n)), (k, i, j, m, pg[i, j, m], po)
