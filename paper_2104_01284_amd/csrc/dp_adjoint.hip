@@ -320,7 +320,7 @@ __device__ inline void block_add5(double g[5], double *gacc)
 // Each workgroup takes a chunk of kAdjChunk consecutive nodes, gathers the
 // ones with rho > 0 into an LDS list (the occupied set is a small part of the
 // grid) and then runs the FP64 work on full waves.
-constexpr int kAdjChunk = 512;
+constexpr int kAdjChunk = 1024;
 
 __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
                                                    const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
@@ -436,8 +436,10 @@ int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t
                          const double *rho, double *rho_next, double *gacc, hipStream_t s)
 {
     const long S = (long)P.n_v * P.n_s * P.n_t;
+    // four workgroups per CU walk the chunks: every chunk is scanned, but
+    // the block reduction of the gradient runs once per workgroup
     long chunks = (S + kAdjChunk - 1) / kAdjChunk;
-    if (chunks > 16384) chunks = 16384;
+    if (chunks > 1024) chunks = 1024;
     hipLaunchKernelGGL(k_adj_stage, dim3((unsigned)chunks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
