@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--kernel", type=int, default=0, help="sweep variant (0 automatic, 1 simple, 2 grouped)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's own sweep configuration instead of the autotuner's")
+    ap.add_argument("--mpc-repeats", type=int, default=20,
+                    help="receding-horizon latency repeats after the timed steps (0 skips)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -194,6 +196,36 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     V0 = float(plan.V0.cpu()[0])
 
+    # end-to-end receding-horizon latency on host clocks: upload of a moved
+    # x0 and signal clock (dp_set_state), the recorded solve, and the copy of
+    # V_0 and u_0* back to the host; the plan build is outside
+    mpc = None
+    if not batched and args.mpc_repeats > 0:
+        import numpy as np
+        g = Plan(insts, store_all=False, graph=True, **opts)
+        rng = np.random.default_rng(11)
+        vlo, vhi, _ = inst["v_grid"]
+        slo, shi, _ = inst["soc_grid"]
+
+        def mpc_step(q):
+            v0 = float(np.clip(inst["v0"] + rng.uniform(-0.5, 0.5), vlo, vhi))
+            s0 = float(np.clip(inst["soc0"] + rng.uniform(-0.01, 0.01), slo, shi))
+            t = time.perf_counter()
+            g.set_state(0, v0, s0, inst["t0_abs"] + 0.5 * q)
+            g.solve()
+            V, u = g.V0.cpu(), g.u0.cpu()
+            assert V.numel() == 1 and u.numel() == 1
+            return (time.perf_counter() - t) * 1e3
+
+        for q in range(3):
+            mpc_step(q)
+        lat = [mpc_step(q) for q in range(args.mpc_repeats)]
+        mpc = {"mean": statistics.mean(lat), "var": statistics.pvariance(lat), "max": max(lat),
+               "median": statistics.median(lat), "repeats": len(lat),
+               "what": "host wall time: dp_set_state (H2D of x0 and signal tables) + recorded dp_solve + "
+                       "D2H of V_0 and u_0*"}
+        del g
+
     # sweep-kernel roofline over one solve: all state-control evaluations of
     # the solve at the canonical FP32 work per evaluation, over the summed
     # duration of its sweep launches
@@ -218,6 +250,7 @@ def main():
                      "max": max(solve_ms), "median": statistics.median(solve_ms)},
         "solve_evals_per_s": evals / (statistics.mean(solve_ms) * 1e-3),
         **parts,
+        "mpc_latency_ms": mpc,
         "V0": V0,
         "V0_all_mean": float(plan.V0.double().mean().cpu()) if batched else V0,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

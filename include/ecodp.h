@@ -141,6 +141,16 @@ int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_
 int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_out,
              int16_t *pi_out, void *scratch, void *stream);
 
+/* Receding horizon (Eq. 6): move instance `inst` to a new initial state
+ * x0 = (v0, soc0, t = 0) at absolute clock t0_abs without rebuilding the plan.
+ * The signal tables (Eq. 8 red sets and the Eq. 5c waits) are recomputed on
+ * the host in FP64 and uploaded with the parameter block through plan-owned
+ * pinned memory, ordered on `stream` before later work; a solve recorded with
+ * DP_GRAPH picks the new state up on its next replay.  v0 >= 0 and soc0 inside
+ * the SoC grid, all finite, else DP_EINVAL with nothing changed.  The stored
+ * values and policy are stale afterwards (dp_adjoint needs a new dp_solve). */
+int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs, void *stream);
+
 /* Forward rollout of the stored policy from x0 with exact FP64 dynamics.
  * traj_dev: double rows [v, xi, t, u, T_eng, T_mot, fuel_g, cost] for stages
  * 0..N of every instance (offset dp_instance_info.traj_offset); the last row's

@@ -19,7 +19,8 @@ DP_TIMING = 2
 DP_GRAPH = 4
 
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_stage",
-           "dp_rollout", "dp_adjoint", "dp_sweep_time", "dp_destroy", "dp_status_string", "dp_last_error")
+           "dp_set_state", "dp_rollout", "dp_adjoint", "dp_sweep_time", "dp_destroy", "dp_status_string",
+           "dp_last_error")
 
 
 class DpProblemDesc(C.Structure):
@@ -74,6 +75,7 @@ def load(require_torch: bool = True):
     lib.dp_instance_info_get.argtypes = [vp, C.c_int32, C.POINTER(DpInstanceInfo)]
     lib.dp_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dp_stage.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
+    lib.dp_set_state.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, vp]
     lib.dp_rollout.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.dp_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dp_sweep_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]

@@ -179,6 +179,16 @@ class Plan:
                                   self._stream()), "dp_stage")
         return J_out, pi_out
 
+    # ---------------------------------------------------------- set_state --
+    def set_state(self, b: int, v0: float, soc0: float, t0_abs: float):
+        """Move instance b to a new x0 = (v0, soc0) at absolute clock t0_abs
+        (receding horizon); ordered on the current stream before later calls."""
+        L.check(self.lib.dp_set_state(self._h, int(b), float(v0), float(soc0), float(t0_abs), self._stream()),
+                "dp_set_state")
+        inst = dict(self.instances[b])
+        inst["v0"], inst["soc0"], inst["t0_abs"] = float(v0), float(soc0), float(t0_abs)
+        self.instances[b] = inst
+
     # ------------------------------------------------------------ rollout --
     def rollout(self):
         """Forward rollout of every instance: (list of [N+1, 8] traj tensors, status [n, 2])."""

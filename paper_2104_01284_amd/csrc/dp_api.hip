@@ -57,6 +57,7 @@ struct Inst {
     size_t tl_dev_off = 0;     // offset (entries) of this instance's TL table in the plan's TL array
     int64_t evals = 0;
     std::vector<int> job_of_k; // grouped sweep: index of the (instance, k) job in the plan's job table
+    std::vector<double> l_cycle, l_red, l_off;   // signals, kept for dp_set_state
 };
 
 // One grouped-sweep launch of a round: the jobs of one (tile, pitch, block)
@@ -110,6 +111,12 @@ struct dp_plan {
     // the stage tables of the next round are built on this stream
     hipStream_t tstream = nullptr;
     hipEvent_t tfork = nullptr, tjoin = nullptr;
+    // dp_set_state: pinned staging of the moved parameter block and signal
+    // tables, reused once the previous upload has been consumed
+    void *state_host = nullptr;
+    size_t state_bytes = 0;
+    hipEvent_t state_ev = nullptr;
+    bool state_pending = false;
     // DP_GRAPH: the captured solve and the buffers it was captured with
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -179,16 +186,16 @@ double gstep(double lo, double hi, int n) { return n > 1 ? (hi - lo) / (n - 1) :
 
 // Signal table of one light: per time node, the red flag and the wait to
 // green (Eq. 5c) in index space; FP64 on the host.
-void build_tl(const dp_problem_desc &d, int L, TLEntry *out)
+// Signal table of one light over the time grid [0, t_f] x n_t (Eq. 5c, 8):
+// red flag and, for a stopped vehicle, the wait to the end of red.
+void build_tl(double C, double R, double O, double t0_abs, double t_f, int n_t, double wt, TLEntry *out)
 {
-    const double ht = gstep(0.0, d.t_f, d.n_t);
-    const double C = d.light_cycle[L], R = d.light_red[L], O = d.light_offset[L];
-    const double wt = d.theta[3];
-    for (int m = 0; m < d.n_t; m++) {
+    const double ht = gstep(0.0, t_f, n_t);
+    for (int m = 0; m < n_t; m++) {
         TLEntry e;
         std::memset(&e, 0, sizeof e);
         const double tm = 0.0 + m * ht;
-        double ph = std::fmod(d.t0_abs + tm - O, C);
+        double ph = std::fmod(t0_abs + tm - O, C);
         if (ph < 0.0) ph += C;
         e.red = ph < R ? 1 : 0;
         e.wc = -1;
@@ -198,9 +205,9 @@ void build_tl(const dp_problem_desc &d, int L, TLEntry *out)
             const double fl = std::floor(delta);
             long c = m + (long)fl;
             double f = delta - fl;
-            if (c > d.n_t - 2) {
-                f += (double)(c - (d.n_t - 2));
-                c = d.n_t - 2;
+            if (c > n_t - 2) {
+                f += (double)(c - (n_t - 2));
+                c = n_t - 2;
             }
             if (f <= 1.0) {
                 e.wc = (int32_t)c;
@@ -604,7 +611,12 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         P.l_off = P.l_red + nl;
         P.light_of_stage = (const int *)put(I.light_of_stage.data(), sizeof(int) * (N + 1));
         P.terminal_V = d.terminal_V ? (const float *)put(d.terminal_V, sizeof(float) * I.S) : nullptr;
-        for (int L = 0; L < nl; L++) build_tl(d, L, host_tl + I.tl_dev_off + (size_t)L * d.n_t);
+        I.l_cycle = lc[b];
+        I.l_red = lr[b];
+        I.l_off = lo[b];
+        for (int L = 0; L < nl; L++)
+            build_tl(lc[b][L], lr[b][L], lo[b][L], d.t0_abs, d.t_f, d.n_t, d.theta[3],
+                     host_tl + I.tl_dev_off + (size_t)L * d.n_t);
 
         const int nst = (p->flags & DP_STORE_ALL_V) ? N + 1 : 2;
         I.J_off = J_off;
@@ -921,7 +933,7 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
     }
     for (size_t b = 0; b < p->inst.size(); b++) {
         const Inst &I = p->inst[b];
-        if (launch_root(I.P, slab_ptr(p, I, J, 1), V0_dev + b, u0_dev + b, s))
+        if (launch_root(p->dev_insts + b, slab_ptr(p, I, J, 1), V0_dev + b, u0_dev + b, s))
             return hip_fail(hipGetLastError(), "root launch");
     }
     return DP_OK;
@@ -1012,6 +1024,53 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
     return DP_OK;
 }
 
+int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs, void *stream)
+{
+    if (!p) return fail(DP_EINVAL, "plan is NULL");
+    if (inst < 0 || inst >= (int)p->inst.size()) return fail(DP_EINVAL, "instance %d out of range", inst);
+    Inst &I = p->inst[inst];
+    if (!(std::isfinite(v0) && v0 >= 0.0 && std::isfinite(soc0) && soc0 >= I.P.s_lo && soc0 <= I.P.s_hi &&
+          std::isfinite(t0_abs)))
+        return fail(DP_EINVAL, "instance %d: x0 outside the grid or not finite", inst);
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const int nl = (int)I.l_cycle.size();
+    const size_t tl_n = (size_t)nl * I.P.n_t;
+    const size_t need = align_up(sizeof(DevInst), 256) + sizeof(TLEntry) * (tl_n ? tl_n : 1);
+    if (p->state_pending) {
+        // the staging buffer is read by the previous upload until it has run
+        if ((e = hipEventSynchronize(p->state_ev)) != hipSuccess) return hip_fail(e, "state upload wait");
+        p->state_pending = false;
+    }
+    if (need > p->state_bytes) {
+        if (p->state_host) (void)hipHostFree(p->state_host);
+        p->state_host = nullptr;
+        p->state_bytes = 0;
+        if ((e = hipHostMalloc(&p->state_host, need, hipHostMallocDefault)) != hipSuccess)
+            return fail(DP_ENOMEM, "pinned staging of %zu bytes: %s", need, hipGetErrorString(e));
+        p->state_bytes = need;
+    }
+    if (!p->state_ev && (e = hipEventCreateWithFlags(&p->state_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "state event");
+    I.P.v0 = v0;
+    I.P.soc0 = soc0;
+    I.P.t0_abs = t0_abs;
+    char *h = (char *)p->state_host;
+    std::memcpy(h, &I.P, sizeof(DevInst));
+    TLEntry *htl = (TLEntry *)(h + align_up(sizeof(DevInst), 256));
+    for (int L = 0; L < nl; L++)
+        build_tl(I.l_cycle[L], I.l_red[L], I.l_off[L], t0_abs, I.P.t_f, I.P.n_t, I.P.wt, htl + (size_t)L * I.P.n_t);
+    e = hipMemcpyAsync(p->dev_insts + inst, h, sizeof(DevInst), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && tl_n)
+        e = hipMemcpyAsync(p->dev_tl + I.tl_dev_off, htl, sizeof(TLEntry) * tl_n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(p->state_ev, s);
+    if (e != hipSuccess) return hip_fail(e, "state upload");
+    p->state_pending = true;
+    p->solved = false;
+    return DP_OK;
+}
+
 int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_dev, int32_t *status_dev, void *stream)
 {
     if (!p) return fail(DP_EINVAL, "plan is NULL");
@@ -1096,6 +1155,11 @@ void dp_destroy(dp_plan *p)
         if (p->join[q]) (void)hipEventDestroy(p->join[q]);
     }
     if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->state_ev) {
+        (void)hipEventSynchronize(p->state_ev);
+        (void)hipEventDestroy(p->state_ev);
+    }
+    if (p->state_host) (void)hipHostFree(p->state_host);
     if (p->tstream) (void)hipStreamDestroy(p->tstream);
     if (p->tfork) (void)hipEventDestroy(p->tfork);
     if (p->tjoin) (void)hipEventDestroy(p->tjoin);

@@ -11,7 +11,7 @@ int launch_terminal(const DevInst &P, float *JN, hipStream_t s);
 int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, hipStream_t s);
 int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const StageEntry *st,
                  const BatEntry *bat, const TLEntry *tl, hipStream_t s);
-int launch_root(const DevInst &P, const float *J1, float *V0, int16_t *u0, hipStream_t s);
+int launch_root(const DevInst *Pdev, const float *J1, float *V0, int16_t *u0, hipStream_t s);
 
 // Grouped sweep geometry: floats per staged plane row (time nodes plus at
 // least one padding column, rounded up to 32 so that the rows of a small grid

@@ -203,9 +203,13 @@ __global__ void __launch_bounds__(1024) k_sweep_naive(DevInst P, int k, const fl
 // Eq. 6 at the actual state x0 = (v0, soc0, t = 0): every control in FP64
 // coordinates and an FP32 value, then a lexicographic (value, u) minimum over
 // the workgroup.
-__global__ void __launch_bounds__(256) k_root(DevInst P, const float *__restrict__ J1, float *V0, int16_t *u0)
+// The parameter block comes from device memory, so that a recorded solve
+// picks up a state moved by dp_set_state.
+__global__ void __launch_bounds__(256) k_root(const DevInst *__restrict__ Pd, const float *__restrict__ J1, float *V0,
+                                              int16_t *u0)
 {
 #pragma clang fp contract(off)
+    const DevInst &P = *Pd;
     __shared__ float sv[256];
     __shared__ int su[256];
     const float Jinf = (float)P.Jinf;
@@ -299,9 +303,9 @@ int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *p
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_root(const DevInst &P, const float *J1, float *V0, int16_t *u0, hipStream_t s)
+int launch_root(const DevInst *Pdev, const float *J1, float *V0, int16_t *u0, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, P, J1, V0, u0);
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, Pdev, J1, V0, u0);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
