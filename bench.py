@@ -40,11 +40,13 @@ PROFILE_NAME = {"realistic": "realistic_2km", "large": "large_3km", "plain": "pl
 
 
 def cpu_baseline(inst, budget_s: float):
-    """The FP64 oracle's backward stages from J_N, timed on the host cores
-    until the budget is spent (at least one stage)."""
+    """The FP64 oracle's backward stages from J_N, timed on all host threads
+    until the budget is spent (at least one stage), then one stage on one
+    thread."""
     import oracle
     I = oracle.Instance(inst)
     J = oracle.terminal(I)
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     done = 0
     k = inst["N"] - 1
@@ -56,10 +58,17 @@ def cpu_baseline(inst, budget_s: float):
             break
     dt = time.perf_counter() - t0
     evals = done * I.S * I.n_u
-    return {"value": evals / dt, "unit": "state-control evals/s", "cores": oracle.num_threads(),
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    oracle.stage(I, max(k, 0), J)
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
+    return {"value": evals / dt, "unit": "state-control evals/s", "cores": cores,
             "kind": "oracle",
+            "value_1core": I.S * I.n_u / dt1,
             "sample": f"{done} backward stages (k={inst['N'] - 1}..{inst['N'] - done}) of {inst['name']} "
-                      f"from J_N, FP64, {evals:.3e} evaluations in {dt:.1f} s"}
+                      f"from J_N, FP64, {evals:.3e} evaluations in {dt:.1f} s on {cores} threads; "
+                      f"one more stage on 1 thread in {dt1:.1f} s"}
 
 
 def measured_traffic(workload, kernel_name):
@@ -93,7 +102,7 @@ def main():
                     help="keep the library's own sweep configuration instead of the autotuner's")
     ap.add_argument("--mpc-repeats", type=int, default=20,
                     help="receding-horizon latency repeats after the timed steps (0 skips)")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (reference for HBM byte counters)")

@@ -76,6 +76,8 @@ def _load():
     lib.or_count_evals.argtypes = [ins]
     lib.or_count_evals.restype = C.c_int64
     lib.or_num_threads.restype = C.c_int
+    lib.or_set_num_threads.argtypes = [C.c_int]
+    lib.or_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -267,3 +269,8 @@ def count_evals(inst):
 
 def num_threads():
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on (for timing)."""
+    _load().or_set_num_threads(int(n))

@@ -857,3 +857,14 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (timing on one core); n < 1 keeps
+ * the current setting. */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

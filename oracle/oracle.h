@@ -99,6 +99,7 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
 int64_t or_count_evals(const or_inst *I);
 
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }
