@@ -44,7 +44,7 @@ struct Inst {
     size_t S = 0;              // slab elements
     std::vector<int> light_of_stage;
     size_t J_off = 0, pi_off = 0, traj_off = 0;
-    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_batj = 0, scr_pw = 0;
+    size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_pw = 0;
     int sweep = 0;             // 1 = simple per-node kernel, 2 = grouped LDS kernel
     int jt = 8;                // SoC rows per workgroup of the grouped kernel
     int nsplit = 1;            // largest number of control slices of any of its stages
@@ -358,7 +358,6 @@ static int plan_rounds(dp_plan *p, size_t scr)
             const long long set = (long long)((r & 1) * I.tab_stride);   // table set of this round
             j.st = (long long)I.scr_st + set;
             j.nf = (long long)I.scr_nf + set;
-            j.batj = (long long)I.scr_batj + set;
             j.rec = (long long)I.scr_rec + set;
             j.pw = (long long)I.scr_pw + set;
             if (I.job_of_k.empty()) I.job_of_k.assign(I.N, -1);
@@ -674,7 +673,8 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             if (jt == 0) jt = 4;
         }
         const bool lds_fits = lds_sweep_bytes(jt, I.H, d.n_t) + lds_job_index_bytes(n_inst) <= lds_cu &&
-                              d.n_t <= 1008 && P.n_u <= 1024 && d.n_v - 1 <= kSortBins;
+                              d.n_t <= 1008 && P.n_u <= 1024 && d.n_v - 1 <= kSortBins &&
+                              I.H <= 120;   // cell offsets in the records are bytes
         I.jt = jt;
         I.sweep = o_kernel == 1 ? 1 : (lds_fits ? 2 : 1);
         if (o_kernel == 2 && !lds_fits) {
@@ -702,9 +702,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             I.scr_pw = scr;
             scr += align_up(sizeof(double) * 2 * (size_t)d.n_v * P.n_u, 256);
             I.scr_rec = scr;
-            scr += align_up(sizeof(float) * (size_t)d.n_v * ntiles * P.n_u * (12 + 2 * I.jt), 256);
-            I.scr_batj = scr;
-            scr += align_up(sizeof(int) * ((size_t)d.n_v * P.n_u * d.n_soc + 16), 256);
+            scr += align_up(sizeof(float) * (size_t)d.n_v * ntiles * P.n_u * (9 + I.jt / 4 + 2 * I.jt), 256);
             I.tab_stride = scr - tab0;
             scr += I.tab_stride;
         } else {

@@ -91,7 +91,7 @@ struct StageJob {
     int tl;                // offset (entries) of the stage's signal table, -1 = none
     int pad;
     long long jn, jk, pik;                 // J_{k+1}, J_k (J buffer), pi_k (pi buffer)
-    long long st, nf, batj, rec, pv, pu;   // stage data and partial results (scratch)
+    long long st, nf, rec, pv, pu;         // stage data and partial results (scratch)
     long long pw;                          // battery power and time step per sorted control (scratch)
 };
 

@@ -133,15 +133,20 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
 }
 
 // Dwords of one packed record: the sorted entry (c, fv, gv, ft, gt, iv, dtc,
-// u), the tile header, padding, then the tile's (fx, gx) pairs.
-__host__ __device__ constexpr int rec_words(int JT) { return 12 + 2 * JT; }
+// u), the tile header, the SoC cells of the tile's rows as int8 offsets from
+// the row (JT / 4 dwords), then the tile's (fx, gx) pairs.
+__host__ __device__ constexpr int rec_cells(int JT) { return 9; }
+__host__ __device__ constexpr int rec_weights(int JT) { return 9 + JT / 4; }
+__host__ __device__ constexpr int rec_words(int JT) { return 9 + JT / 4 + 2 * JT; }
+// Cell offset of a row without a feasible successor (or past the tile).
+constexpr int kNoCell = -128;
 
 // Battery coordinates of one (speed node, SoC tile, sorted position), written
 // as one packed record per (speed node, tile, position) so that the sweep
 // stages a run of controls with one contiguous copy: per SoC node the lower
-// cell (also kept in batj for the general path) and the weights (fx, gx);
-// the header is the first node's cell when the tile's cells are consecutive
-// (jx0 + q), else -1.  One lane per (record, SoC row): the JT lanes of a
+// cell (as an offset from the node) and the weights (fx, gx); the header is
+// the first node's cell when the tile's cells are consecutive (jx0 + q), else
+// -1.  One lane per (record, SoC row): the JT lanes of a
 // record are consecutive and aligned (JT divides the wave), consecutive
 // records are consecutive in memory, and the battery power and time step of
 // the control come from the sort (no second powertrain evaluation).
@@ -154,7 +159,6 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
     const SortedEntry *__restrict__ st = (const SortedEntry *)(B.scr + jb.st);
     const double2 *__restrict__ pw = (const double2 *)(B.scr + jb.pw);
     const int *__restrict__ nfeas = (const int *)(B.scr + jb.nf);
-    int *__restrict__ batj = (int *)(B.scr + jb.batj);
     float *__restrict__ rec = (float *)(B.scr + jb.rec);
     const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long total = (long)P.n_v * ntiles * P.n_u * JT;
@@ -180,7 +184,6 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
             const double rs = (double)j - (pd.y * I) / (P.Cnom * P.hs);
             if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
         }
-        batj[ir * P.n_s + j] = jx;
     }
     // consecutive cells across the record's rows q < jc
     const int lane = threadIdx.x & 63;
@@ -192,11 +195,13 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
     const bool regular = (bad & grp) == 0;
     const int CW = rec_words(JT);
     float *out = rec + (((long)i * ntiles + tile) * P.n_u + r) * CW;
-    out[12 + 2 * q] = jx >= 0 ? (float)fx : 0.0f;
-    out[13 + 2 * q] = jx >= 0 ? (float)(1.0 - fx) : 0.0f;
+    const int WO = rec_weights(JT);
+    out[WO + 2 * q] = jx >= 0 ? (float)fx : 0.0f;
+    out[WO + 2 * q + 1] = jx >= 0 ? (float)(1.0 - fx) : 0.0f;
+    // the row's cell as a byte offset from the row (|offset| <= H + 1 < 127)
+    reinterpret_cast<int8_t *>(out + rec_cells(JT))[q] = (int8_t)(jx >= 0 ? jx - (j0 + q) : kNoCell);
     const float *ef = reinterpret_cast<const float *>(&st[ir]);
-    for (int w = q; w < 12; w += JT)
-        out[w] = w < 8 ? ef[w] : (w == 8 ? __int_as_float(regular ? jx0 : -1) : 0.0f);
+    for (int w = q; w < 9; w += JT) out[w] = w < 8 ? ef[w] : __int_as_float(regular ? jx0 : -1);
 }
 
 // ------------------------------------------------------------------ sweep --
@@ -292,7 +297,6 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     int16_t *__restrict__ pik = B.pik ? B.pik : (int16_t *)(B.pi + jb.pik);
     const int *__restrict__ nfeas = (const int *)(B.scr + jb.nf);
     const float *__restrict__ rec = (const float *)(B.scr + jb.rec);
-    const int *__restrict__ batj = (const int *)(B.scr + jb.batj);
     const TLEntry *__restrict__ tl = jb.tl >= 0 ? B.tl + jb.tl : nullptr;
     float *__restrict__ part_v = (float *)(B.scr + jb.pv);
     int16_t *__restrict__ part_u = (int16_t *)(B.scr + jb.pu);
@@ -420,7 +424,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             const int jx0 = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
             const int pos = m + dtc;
             const bool regular = jx0 >= wlo && jx0 + jc <= whi;
-            const float *wp = ce + 12;
+            const float *wp = ce + rec_weights(JT);
             float Qv[JT];
             if (regular && jc == JT) {
                 // successor times past the grid read the padding columns
@@ -444,10 +448,14 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                 // lanes whose successor time is off the grid get an infinite
                 // stage cost, so their candidates never win
                 const float c = okt ? c0f : __builtin_inff();
-                const int r = c0 + cr;
+                // the rows' cells, four int8 offsets per dword (wave-uniform)
+                int cw[JT / 4];
+#pragma unroll
+                for (int w = 0; w < JT / 4; w++) cw[w] = __builtin_amdgcn_readfirstlane(__float_as_int(ce[rec_cells(JT) + w]));
 #pragma unroll
                 for (int q = 0; q < JT; q++) {
-                    const int jx = q < jc ? __builtin_amdgcn_readfirstlane(batj[((long)i * nu + r) * ns + j0 + q]) : -1;
+                    const int off = (int)(int8_t)(cw[q / 4] >> (8 * (q % 4)));
+                    const int jx = q < jc && off != kNoCell ? j0 + q + off : -1;
                     Qv[q] = Jinf;
                     if (jx >= 0) {
                         float V0, V1;
