@@ -695,8 +695,8 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         const size_t tab0 = scr;
         I.scr_st = scr;
         scr += align_up(sizeof(SortedEntry) * d.n_v * P.n_u, 256);
-        I.scr_nf = scr;
-        scr += align_up(sizeof(int) * d.n_v, 256);
+        I.scr_nf = scr;   // feasible-control counts, then the speed nodes in decreasing order of work
+        scr += align_up(sizeof(int) * 2 * (size_t)d.n_v, 256);
         if (I.sweep == 2) {
             const size_t ntiles = (d.n_soc + I.jt - 1) / I.jt;
             I.scr_pw = scr;

@@ -132,6 +132,35 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
     }
 }
 
+// Speed nodes of a job in decreasing order of the work they carry (feasible
+// controls; none above the stage's speed limit), ties by node index, so
+// that the sweep hands out its longest items first.
+__global__ void __launch_bounds__(256) k_stage_rank(StageBase B)
+{
+    const StageJob &jb = B.jobs[blockIdx.x];
+    const DevInst &P = B.insts[jb.inst];
+    const int *__restrict__ nfeas = (const int *)(B.scr + jb.nf);
+    int *__restrict__ order = (int *)(B.scr + jb.nf) + P.n_v;
+    const int nv = P.n_v, k = jb.k;
+    auto work = [&](int i) {
+        double v;
+        {
+#pragma clang fp contract(off)
+            v = P.v_lo + i * P.hv;
+        }
+        return v > P.vmax[k] ? 0 : nfeas[i];
+    };
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const int w = work(i);
+        int rank = 0;
+        for (int o = 0; o < nv; o++) {
+            const int wo = work(o);
+            rank += (wo > w || (wo == w && o < i)) ? 1 : 0;
+        }
+        order[rank] = i;
+    }
+}
+
 // Dwords of one packed record: the sorted entry (c, fv, gv, ft, gt, iv, dtc,
 // u), the tile header, the SoC cells of the tile's rows as int8 offsets from
 // the row (JT / 4 dwords), then the tile's (fx, gx) pairs.
@@ -239,9 +268,11 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     float *lds = lds_base + ibw;
     // Persistent workgroups take (job, speed node, SoC tile, control slice)
     // items from eight queues, one contiguous band of items per XCD (blocks
-    // are dealt round-robin over the 8 XCDs, so a band stays in one L2); a
-    // workgroup whose band is drained takes items from the other bands.
-    // Every workgroup exits once all queues are drained.
+    // are dealt round-robin over the 8 XCDs, so a band's next-stage planes
+    // stay in one L2); a job's speed nodes come in decreasing order of work,
+    // which keeps a band's nodes close in speed and leaves the shortest items
+    // for the end.  A workgroup whose band is drained takes items from the
+    // other bands; every workgroup exits once all queues are drained.
     __shared__ int s_item, s_job;
     const int home = blockIdx.x & 7;
     int qi = 0;
@@ -301,8 +332,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     float *__restrict__ part_v = (float *)(B.scr + jb.pv);
     int16_t *__restrict__ part_u = (int16_t *)(B.scr + jb.pu);
     const int nt = P.n_t, ns = P.n_s, nu = P.n_u;
-    const int i = item / (ntiles * nsplit);
-    const int rem = item - i * ntiles * nsplit;
+    const int ir = item / (ntiles * nsplit);
+    const int rem = item - ir * ntiles * nsplit;
+    // speed nodes in decreasing order of work (written after the counts)
+    const int i = __builtin_amdgcn_readfirstlane(nfeas[P.n_v + ir]);
     const int tile = rem / nsplit;
     const int split = rem - tile * nsplit;
     const int j0 = tile * JT;
@@ -580,6 +613,8 @@ __global__ void k_sweep_combine(StageBase B)
 int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_records, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stage_sort, dim3(max_nv, njobs), dim3(1024), 0, s, B);
+    if (hipGetLastError() != hipSuccess) return -1;
+    hipLaunchKernelGGL(k_stage_rank, dim3(njobs), dim3(256), 0, s, B);
     if (hipGetLastError() != hipSuccess) return -1;
     hipLaunchKernelGGL(k_stage_bat_sorted, dim3((unsigned)((max_records + 255) / 256), njobs), dim3(256), 0, s, B);
     // (max_records counts record lanes: records x SoC rows per record)
