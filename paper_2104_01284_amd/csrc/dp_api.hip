@@ -58,6 +58,7 @@ struct Inst {
     int64_t evals = 0;
     std::vector<int> job_of_k; // grouped sweep: index of the (instance, k) job in the plan's job table
     std::vector<double> l_cycle, l_red, l_off;   // signals, kept for dp_set_state
+    std::vector<char> same_tables;               // [k]: stage k's tables equal stage k+1's
 };
 
 // One grouped-sweep launch of a round: the jobs of one (tile, pitch, block)
@@ -76,6 +77,10 @@ struct Round {
     int job_begin = 0, njobs = 0;      // grouped-sweep jobs, ordered by launch
     int max_nv = 0;
     long max_records = 0, max_nodes = 0;
+    // jobs whose stage tables differ from their instance's previous stage
+    // (the others reuse the table set of the previous round)
+    int bjob_begin = 0, nbjobs = 0, bmax_nv = 0;
+    long bmax_records = 0;
     bool any_split = false;
     std::vector<SweepLaunch> sweeps;
     std::vector<int> simple;           // instances on the simple per-node sweep
@@ -97,6 +102,8 @@ struct dp_plan {
     int n_ev_used = 0;
     // grouped sweep tables: parameter blocks, jobs, per-launch item offsets
     std::vector<StageJob> jobs;
+    std::vector<StageJob> bjobs;     // per round, the jobs that build stage tables
+    StageJob *dev_bjobs = nullptr;
     std::vector<Round> rounds;
     void *dev_tables = nullptr;
     DevInst *dev_insts = nullptr;
@@ -298,6 +305,7 @@ static int plan_rounds(dp_plan *p, size_t scr)
     p->rounds.assign(maxN, Round{});
     std::vector<int> ib;
     int q_slot = 0;
+    std::vector<int> cur_set(n_inst, -1);   // table set holding each instance's latest tables
     // about 32 items per CU (six or more per resident workgroup), so that
     // the last items of a launch are short against the whole; a slice costs
     // a partial-result store and a share of the combine
@@ -355,7 +363,12 @@ static int plan_rounds(dp_plan *p, size_t scr)
             j.jn = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k + 1 : ((k + 1) & 1)));
             j.jk = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k : (k & 1)));
             j.pik = (long long)(I.pi_off + sizeof(int16_t) * I.S * (size_t)k);
-            const long long set = (long long)((r & 1) * I.tab_stride);   // table set of this round
+            // the previous round's set when stage k's tables equal stage k+1's,
+            // else the other set (its last reader precedes this round)
+            const bool reuse = cur_set[t[q].b] >= 0 && I.same_tables[k];
+            const int tset = reuse ? cur_set[t[q].b] : (cur_set[t[q].b] < 0 ? 0 : 1 - cur_set[t[q].b]);
+            cur_set[t[q].b] = tset;
+            const long long set = (long long)(tset * I.tab_stride);
             j.st = (long long)I.scr_st + set;
             j.nf = (long long)I.scr_nf + set;
             j.rec = (long long)I.scr_rec + set;
@@ -363,6 +376,13 @@ static int plan_rounds(dp_plan *p, size_t scr)
             if (I.job_of_k.empty()) I.job_of_k.assign(I.N, -1);
             I.job_of_k[k] = (int)p->jobs.size();
             p->jobs.push_back(j);
+            if (!reuse) {
+                if (R.nbjobs == 0) R.bjob_begin = (int)p->bjobs.size();
+                R.nbjobs++;
+                R.bmax_nv = std::max(R.bmax_nv, I.P.n_v);
+                R.bmax_records = std::max(R.bmax_records, (long)I.P.n_v * I.P.n_u * j.ntiles * I.jt);
+                p->bjobs.push_back(j);
+            }
             R.max_nv = std::max(R.max_nv, I.P.n_v);
             R.max_records = std::max(R.max_records, (long)I.P.n_v * I.P.n_u * j.ntiles * I.jt);
             R.max_nodes = std::max(R.max_nodes, (long)I.S);
@@ -420,6 +440,10 @@ static int plan_rounds(dp_plan *p, size_t scr)
         j.pv = (long long)p->inst[j.inst].scr_pv;
         j.pu = (long long)p->inst[j.inst].scr_pu;
     }
+    for (StageJob &j : p->bjobs) {
+        j.pv = (long long)p->inst[j.inst].scr_pv;
+        j.pu = (long long)p->inst[j.inst].scr_pu;
+    }
     p->n_q_slots = q_slot + 1;
     p->scr_q = scr;
     scr += align_up(sizeof(int) * 8 * (size_t)p->n_q_slots, 256);
@@ -428,17 +452,21 @@ static int plan_rounds(dp_plan *p, size_t scr)
     const size_t b_inst = align_up(sizeof(DevInst) * n_inst, 256);
     const size_t b_jobs = align_up(sizeof(StageJob) * std::max<size_t>(1, p->jobs.size()), 256);
     const size_t b_ib = align_up(sizeof(int) * std::max<size_t>(1, ib.size()), 256);
-    hipError_t e = hipMalloc(&p->dev_tables, b_inst + b_jobs + b_ib);
-    if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu table bytes: %s", b_inst + b_jobs + b_ib,
+    const size_t b_bj = align_up(sizeof(StageJob) * std::max<size_t>(1, p->bjobs.size()), 256);
+    hipError_t e = hipMalloc(&p->dev_tables, b_inst + b_jobs + b_ib + b_bj);
+    if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu table bytes: %s", b_inst + b_jobs + b_ib + b_bj,
                                      hipGetErrorString(e));
-    std::vector<unsigned char> host(b_inst + b_jobs + b_ib, 0);
+    std::vector<unsigned char> host(b_inst + b_jobs + b_ib + b_bj, 0);
     for (int b = 0; b < n_inst; b++) std::memcpy(host.data() + sizeof(DevInst) * b, &p->inst[b].P, sizeof(DevInst));
     if (!p->jobs.empty()) std::memcpy(host.data() + b_inst, p->jobs.data(), sizeof(StageJob) * p->jobs.size());
     if (!ib.empty()) std::memcpy(host.data() + b_inst + b_jobs, ib.data(), sizeof(int) * ib.size());
+    if (!p->bjobs.empty())
+        std::memcpy(host.data() + b_inst + b_jobs + b_ib, p->bjobs.data(), sizeof(StageJob) * p->bjobs.size());
     char *d = (char *)p->dev_tables;
     p->dev_insts = (DevInst *)d;
     p->dev_jobs = (StageJob *)(d + b_inst);
     p->dev_ib = (int *)(d + b_inst + b_jobs);
+    p->dev_bjobs = (StageJob *)(d + b_inst + b_jobs + b_ib);
     if ((e = hipMemcpy(p->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "table upload");
     return DP_OK;
@@ -610,6 +638,12 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         P.l_off = P.l_red + nl;
         P.light_of_stage = (const int *)put(I.light_of_stage.data(), sizeof(int) * (N + 1));
         P.terminal_V = d.terminal_V ? (const float *)put(d.terminal_V, sizeof(float) * I.S) : nullptr;
+        // the stage tables of k depend on k only through the grade of step k
+        // and the speed limits at k and k+1
+        I.same_tables.assign(N, 0);
+        for (int k = 0; k + 1 < N; k++)
+            I.same_tables[k] = cosa[b][k] == cosa[b][k + 1] && sina[b][k] == sina[b][k + 1] &&
+                               vmax[b][k] == vmax[b][k + 1] && vmax[b][k + 1] == vmax[b][k + 2];
         I.l_cycle = lc[b];
         I.l_red = lr[b];
         I.l_off = lo[b];
@@ -878,21 +912,24 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
         if (pre) {
             hipError_t e = hipStreamWaitEvent(s, p->tjoin, 0);
             if (e != hipSuccess) return hip_fail(e, "table join");
-        } else if (launch_stage_jobs(B, R.njobs, R.max_nv, R.max_records, s)) {
-            return hip_fail(hipGetLastError(), "stage table launch");
+        } else if (R.nbjobs > 0) {
+            StageBase Bt = base;
+            Bt.jobs = p->dev_bjobs + R.bjob_begin;
+            if (launch_stage_jobs(Bt, R.nbjobs, R.bmax_nv, R.bmax_records, s))
+                return hip_fail(hipGetLastError(), "stage table launch");
         }
         // the next round's tables (the other table set, last read by the
         // previous round, which is already ordered before this point) are
         // built beside this round's sweep
         pre = false;
-        if (p->tstream && r + 1 < p->rounds.size() && p->rounds[r + 1].njobs > 0) {
+        if (p->tstream && r + 1 < p->rounds.size() && p->rounds[r + 1].nbjobs > 0) {
             const Round &R1 = p->rounds[r + 1];
             StageBase B1 = base;
-            B1.jobs = p->dev_jobs + R1.job_begin;
+            B1.jobs = p->dev_bjobs + R1.bjob_begin;
             hipError_t e = hipEventRecord(p->tfork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(p->tstream, p->tfork, 0);
             if (e != hipSuccess) return hip_fail(e, "table fork");
-            if (launch_stage_jobs(B1, R1.njobs, R1.max_nv, R1.max_records, p->tstream))
+            if (launch_stage_jobs(B1, R1.nbjobs, R1.bmax_nv, R1.bmax_records, p->tstream))
                 return hip_fail(hipGetLastError(), "stage table launch");
             if ((e = hipEventRecord(p->tjoin, p->tstream)) != hipSuccess) return hip_fail(e, "table join");
             pre = true;
