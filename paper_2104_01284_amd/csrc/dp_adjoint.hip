@@ -298,19 +298,45 @@ __global__ void k_adj_root(DevInst P, const float *__restrict__ J1, const int16_
     scatter(P, rho1, 1.0, x, false);
 }
 
-__device__ inline void block_add5(double g[5], double *gacc)
+// Workgroups of the adjoint kernels (each owns a slot of partial gradient
+// sums, so no two workgroups add into the same memory).
+constexpr int kAdjBlocks = 1024;
+
+// Sum g over the workgroup (wave shuffles, then one LDS step) and add it to
+// the workgroup's own slot gpart[blockIdx.x][0..4].
+__device__ inline void block_add5(double g[5], double *gpart)
 {
-    __shared__ double red[5][256];
-    for (int q = 0; q < 5; q++) red[q][threadIdx.x] = g[q];
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int q = 0; q < 5; q++) red[q][threadIdx.x] += red[q][threadIdx.x + s];
-        __syncthreads();
+    __shared__ double red[16][5];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < 5; q++) {
+        double x = g[q];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) red[w][q] = x;
     }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 5; q++)
-            if (red[q][0] != 0.0) unsafeAtomicAdd(&gacc[q], red[q][0]);
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double x = 0.0;
+        for (int ww = 0; ww < nw; ww++) x += red[ww][threadIdx.x];
+        gpart[(long)blockIdx.x * 5 + threadIdx.x] += x;
+    }
+}
+
+// grad[q] += sum over the kAdjBlocks slots of component q.
+__global__ void __launch_bounds__(256) k_adj_reduce(const double *__restrict__ gpart, double *__restrict__ grad)
+{
+    __shared__ double red[4][5];
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < kAdjBlocks; b += blockDim.x)
+        for (int q = 0; q < 5; q++) g[q] += gpart[(long)b * 5 + q];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < 5; q++) {
+        double x = g[q];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) red[w][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) grad[threadIdx.x] += red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                               red[3][threadIdx.x];
 }
 
 // Stage k >= 1: every node with occupancy rho > 0 follows its stored control:
@@ -320,7 +346,7 @@ __device__ inline void block_add5(double g[5], double *gacc)
 // Each workgroup takes a chunk of kAdjChunk consecutive nodes, gathers the
 // ones with rho > 0 into an LDS list (the occupied set is a small part of the
 // grid) and then runs the FP64 work on full waves.
-constexpr int kAdjChunk = 1024;
+constexpr int kAdjChunk = 512;
 
 __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
                                                    const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
@@ -425,6 +451,12 @@ int launch_fill_f64(double *p, long n, double v, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int launch_adjoint_reduce(const double *gpart, double *grad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, gpart, grad);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
                         hipStream_t s)
 {
@@ -435,19 +467,14 @@ int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, do
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
                          const double *rho, double *rho_next, double *gacc, hipStream_t s)
 {
-    const long S = (long)P.n_v * P.n_s * P.n_t;
-    // four workgroups per CU walk the chunks: every chunk is scanned, but
-    // the block reduction of the gradient runs once per workgroup
-    long chunks = (S + kAdjChunk - 1) / kAdjChunk;
-    if (chunks > 1024) chunks = 1024;
-    hipLaunchKernelGGL(k_adj_stage, dim3((unsigned)chunks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
+    // kAdjBlocks workgroups walk the chunks, each adding into its own slot
+    hipLaunchKernelGGL(k_adj_stage, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_adjoint_terminal(const DevInst &P, const float *JN, const double *rho, double *gacc, hipStream_t s)
 {
-    const long S = (long)P.n_v * P.n_s * P.n_t;
-    hipLaunchKernelGGL(k_adj_terminal, dim3(grid_for(S)), dim3(256), 0, s, P, JN, rho, gacc);
+    hipLaunchKernelGGL(k_adj_terminal, dim3(kAdjBlocks), dim3(256), 0, s, P, JN, rho, gacc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -110,6 +110,7 @@ struct dp_plan {
     StageJob *dev_jobs = nullptr;
     int *dev_ib = nullptr;
     size_t scr_q = 0;                // 8 queue counters per sweep launch, then 8 for dp_stage
+    size_t scr_gpart = 0;            // adjoint partial gradient sums
     int n_q_slots = 0;
     // independent sweep launches of a round run on these streams side by side
     static constexpr int kSide = 3;
@@ -447,6 +448,8 @@ static int plan_rounds(dp_plan *p, size_t scr)
     p->n_q_slots = q_slot + 1;
     p->scr_q = scr;
     scr += align_up(sizeof(int) * 8 * (size_t)p->n_q_slots, 256);
+    p->scr_gpart = scr;   // adjoint: per-workgroup partial gradient sums
+    scr += align_up(sizeof(double) * 5 * 1024, 256);
     p->bytes_scratch = scr;
 
     const size_t b_inst = align_up(sizeof(DevInst) * n_inst, 256);
@@ -1139,7 +1142,9 @@ int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
         double *g = grad_dev + 5 * b;
         const float *Jb = (const float *)((const char *)J + I.J_off);
         const int16_t *pib = (const int16_t *)((const char *)pi + I.pi_off);
-        if (launch_fill_f64(g, 5, 0.0, s) || launch_fill_f64(rho_a, (long)I.S, 0.0, s))
+        double *gpart = (double *)((char *)scratch + p->scr_gpart);
+        if (launch_fill_f64(g, 5, 0.0, s) || launch_fill_f64(rho_a, (long)I.S, 0.0, s) ||
+            launch_fill_f64(gpart, 5L * 1024, 0.0, s))
             return hip_fail(hipGetLastError(), "fill launch");
         if (launch_adjoint_root(I.P, Jb + I.S, u0_dev + b, rho_a, g, s))
             return hip_fail(hipGetLastError(), "adjoint root launch");
@@ -1147,14 +1152,16 @@ int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
             const int L = I.light_of_stage[k];
             const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
             if (launch_fill_f64(rho_b, (long)I.S, 0.0, s)) return hip_fail(hipGetLastError(), "fill launch");
-            if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, rho_a, rho_b, g, s))
+            if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, rho_a, rho_b, gpart,
+                                     s))
                 return hip_fail(hipGetLastError(), "adjoint stage launch");
             double *t = rho_a;
             rho_a = rho_b;
             rho_b = t;
         }
-        if (launch_adjoint_terminal(I.P, Jb + (size_t)I.N * I.S, rho_a, g, s))
+        if (launch_adjoint_terminal(I.P, Jb + (size_t)I.N * I.S, rho_a, gpart, s))
             return hip_fail(hipGetLastError(), "adjoint terminal launch");
+        if (launch_adjoint_reduce(gpart, g, s)) return hip_fail(hipGetLastError(), "adjoint reduce launch");
     }
     return DP_OK;
 }

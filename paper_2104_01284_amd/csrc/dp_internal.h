@@ -39,6 +39,9 @@ int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, do
                         hipStream_t s);
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
                          const double *rho, double *rho_next, double *gacc, hipStream_t s);
+// gpart: the adjoint kernels' per-workgroup partial gradient sums (1024 x 5
+// doubles, zeroed before the first stage); grad += their sum.
+int launch_adjoint_reduce(const double *gpart, double *grad, hipStream_t s);
 int launch_adjoint_terminal(const DevInst &P, const float *JN, const double *rho, double *gacc, hipStream_t s);
 
 }  // namespace ecodp
