@@ -307,10 +307,11 @@ static int plan_rounds(dp_plan *p, size_t scr)
     std::vector<int> ib;
     int q_slot = 0;
     std::vector<int> cur_set(n_inst, -1);   // table set holding each instance's latest tables
-    // about 32 items per CU (six or more per resident workgroup), so that
-    // the last items of a launch are short against the whole; a slice costs
-    // a partial-result store and a share of the combine
-    const long target = 32L * p->n_cu;
+    // about 20 items per CU, so that the last items of a launch are short
+    // against the whole; a slice costs a partial-result store and a share
+    // of the combine (measured best: 8-10 slices on realistic_2km, 4 on
+    // large_3km)
+    const long target = 20L * p->n_cu;
     for (int r = 0; r < maxN; r++) {
         Round &R = p->rounds[r];
         long base = 0;
