@@ -23,8 +23,13 @@
  *  - Buffers named *_dev and the J / pi / scratch buffers are DEVICE memory
  *    owned by the caller, borrowed until the enqueued work completes.  Sizes
  *    come from dp_workspace_size(); per-instance offsets from dp_instance_info().
- *    The plan owns only host metadata and a small device parameter block.
- *  - A plan must not be used from two host threads at once.
+ *    The plan owns host metadata, a small device block of parameters and job
+ *    tables, a few streams and events of its own (work it puts on them is
+ *    joined back into the caller's stream before the call's later work), a
+ *    recorded graph (DP_GRAPH) and a small pinned staging buffer
+ *    (dp_set_state); dp_destroy releases them.
+ *  - A plan must not be used from two host threads at once, and its calls on
+ *    different streams must not overlap (they share the scratch buffer).
  *
  * Data layouts (all row-major, travel time fastest):
  *  - value slab J_k: float [n_v][n_soc][n_t]; policy slab pi_k: int16 [n_v][n_soc][n_t]
@@ -127,17 +132,29 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
  * dp_rollout and dp_adjoint (all instances of the plan). */
 int dp_workspace_size(const dp_plan *p, size_t *bytes_J, size_t *bytes_pi, size_t *bytes_scratch);
 
+/* Sizes, buffer offsets and the state-sweep configuration chosen for instance
+ * `inst` (0 <= inst < n_inst). */
 int dp_instance_info_get(const dp_plan *p, int32_t inst, dp_instance_info *info);
 
 /* Backward recursion Eq. 9a-d for every instance: J_N (Eq. 9a), then for
  * k = N-1..0 the stage table and the state sweep (min and argmin over all
  * controls at every node), then the exact first step at x0 (Eq. 6):
- * V0_dev[inst] = min(J_inf, min_u c + interp J_1), u0_dev[inst] = argmin or -1. */
+ * V0_dev[inst] = min(J_inf, min_u c + interp J_1), u0_dev[inst] = argmin or -1.
+ * All instances run in rounds of one stage each (round r: stage N_b-1-r of
+ * every instance b with N_b > r); each instance's results are bit for bit
+ * those of a plan holding it alone.  Among exactly equal candidates the
+ * grouped sweep keeps the first in its visit order (successor speed cell,
+ * then control index); the simple sweep keeps the lowest control index.
+ * With DP_GRAPH the launches are recorded into a HIP graph on the first call
+ * (and again whenever the buffers differ from the recorded ones) and the
+ * graph is replayed on `stream`. */
 int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev,
              void *stream);
 
 /* One backward step k of instance `inst` from a caller-provided J_{k+1} slab
- * (device float [n_v][n_soc][n_t]) into J_out / pi_out (device slabs). */
+ * (device float [n_v][n_soc][n_t]) into J_out / pi_out (device slabs, not
+ * aliasing J_next), with the configuration dp_solve uses for that stage; the
+ * stage tables are rebuilt in `scratch`. */
 int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_out,
              int16_t *pi_out, void *scratch, void *stream);
 

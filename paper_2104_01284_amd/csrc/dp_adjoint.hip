@@ -438,8 +438,8 @@ static int grid_for(long n)
     return (int)b;
 }
 
-int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, const TLEntry *, double *traj,
-                   int32_t *status, hipStream_t s)
+int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, double *traj, int32_t *status,
+                   hipStream_t s)
 {
     hipLaunchKernelGGL(k_rollout, dim3(1), dim3(64), 0, s, P, pi, u0, traj, status);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -1120,7 +1120,7 @@ int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_d
     for (size_t b = 0; b < p->inst.size(); b++) {
         const Inst &I = p->inst[b];
         const int16_t *pib = (const int16_t *)((const char *)pi + I.pi_off);
-        if (launch_rollout(I.P, pib, u0_dev + b, nullptr, traj_dev + I.traj_off, status_dev + 2 * b, s))
+        if (launch_rollout(I.P, pib, u0_dev + b, traj_dev + I.traj_off, status_dev + 2 * b, s))
             return hip_fail(hipGetLastError(), "rollout launch");
     }
     return DP_OK;

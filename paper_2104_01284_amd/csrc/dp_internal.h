@@ -32,8 +32,8 @@ int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int nj
 int launch_combine_jobs(const StageBase &B, int njobs, long max_nodes, hipStream_t s);
 int launch_fill_i32(int *p, long n, int v, hipStream_t s);
 
-int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, const TLEntry *unused,
-                   double *traj, int32_t *status, hipStream_t s);
+int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, double *traj, int32_t *status,
+                   hipStream_t s);
 int launch_fill_f64(double *p, long n, double v, hipStream_t s);
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
                         hipStream_t s);
