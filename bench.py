@@ -71,18 +71,25 @@ def cpu_baseline(inst, budget_s: float):
                       f"one more stage on 1 thread in {dt1:.1f} s"}
 
 
-def measured_traffic(workload, kernel_name):
+def sweep_pitch(n_t):
+    """LDS row pitch of the grouped sweep (its PITCH template argument): the
+    time nodes plus one padding column, rounded up to 32."""
+    return (n_t + 1 + 31) // 32 * 32
+
+
+def measured_traffic(workload, kernel_name, split):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
-    of this workload, if it was measured on the current sweep source and the
-    same kernel instance; else None."""
+    of this workload, if it was measured on the current sweep source, the
+    same kernel instance and the same number of control slices; else None."""
     import re
     from paper_2104_01284_amd.profiling import sweep_source_hash
     path = os.path.join(ROOT, "profiles", f"sweep_{PROFILE_NAME.get(workload, workload)}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch=(\S+) sweep_source=(\S+)", text)
-    if not m or m.group(2) != sweep_source_hash() or kernel_name not in text.split("\n")[0]:
+    m = re.search(r"traffic_bytes_per_launch=(\S+) sweep_source=(\S+) split=(\S+)", text)
+    if (not m or m.group(2) != sweep_source_hash() or m.group(3) != str(split)
+            or kernel_name not in text.split("\n")[0]):
         return None
     return float(m.group(1))
 
@@ -265,7 +272,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": None if batched else measured_traffic(
-                         args.workload, f"k_sweep_lds<{int(info.sweep_tile)}, {64 * ((int(info.n_t) + 63) // 64)}>"),
+                         args.workload, f"k_sweep_lds<{int(info.sweep_tile)}, {sweep_pitch(int(info.n_t))}>",
+                         int(info.sweep_split)),
                      "traffic_unit": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "state sweep", "avg_launch_ms": avg_launch_ms, "launches_per_solve": launches,
                      "flops_per_launch": FLOPS_PER_EVAL * evals / max(1, launches)},

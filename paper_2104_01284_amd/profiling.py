@@ -74,7 +74,10 @@ def sweep_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib, needle):
+def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib, needle, split="?"):
+    """Copy-calibrated HBM bytes per launch of the kernels matching `needle`;
+    `split` is the number of control slices of the profiled run (the byte
+    count depends on it)."""
     copy_kib = float(copy_mib) * 1024.0
 
     def copy_factor(db, counter):
@@ -95,7 +98,7 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib, needle):
         tot = max(tot, b)
         print(f"{name.split('(')[0][:60]:60s} dispatches={n:5d} FETCH={fk:12.1f} KiB WRITE={wk:12.1f} KiB "
               f"-> HBM bytes/dispatch {b:.4e}")
-    print(f"traffic_bytes_per_launch={tot:.6e} sweep_source={sweep_source_hash()}")
+    print(f"traffic_bytes_per_launch={tot:.6e} sweep_source={sweep_source_hash()} split={split}")
 
 
 if __name__ == "__main__":
@@ -104,6 +107,6 @@ if __name__ == "__main__":
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:8])
+        traffic(*sys.argv[2:9])
     else:
         trace(sys.argv[1])

@@ -287,3 +287,22 @@ def test_large_last_stages_and_sampled_isolated(torch):
             assert abs(Jg[i, j, m] - Jo_n) <= REL_J * max(1.0, abs(Jo_n)), (k, i, j, m, Jg[i, j, m], Jo_n)
             if pg[i, j, m] != po:
                 assert q2 - Jo_n < REL_GAP * max(1.0, abs(Jo_n)), (k, i, j, m, pg[i, j, m], po)
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_paper_shape_end_to_end_and_isolated(torch, kernel):
+    """The paper's own grid (Sec. IV: 20 steps, 35x26x40 states, 23x30
+    controls): end-to-end V_0 and J against the oracle, and every stage
+    isolated, for the paper-style per-state kernel and the grouped sweep."""
+    inst = ins.paper_shape()
+    say("paper_shape kernel", kernel)
+    r = oracle.solve(inst, q2=True)
+    plan = Plan([inst], store_all=True, kernel=kernel)
+    V0, u0 = plan.solve()
+    torch.cuda.synchronize()
+    assert abs(float(V0.cpu()[0]) - r["V0"]) <= 1e-4 * abs(r["V0"])
+    J = plan.values(0).cpu().numpy().astype(np.float64)
+    err = np.abs(J - r["J"]) / np.maximum(1.0, np.abs(r["J"]))
+    assert err.max() < 1e-4, float(err.max())
+    for k in range(inst["N"]):
+        check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), "paper_shape")
