@@ -44,8 +44,9 @@ struct StageEntry {
 // visits it: ascending next-stage speed cell, ascending control inside a cell.
 struct SortedEntry {
     float c;
-    float fv, gv;
-    float ft, gt;
+    float fv, gv;  // speed weights of the upper and lower successor cell
+    float ft;      // time fraction inside the successor cell
+    float rt;      // ft / gt: the time lerp is gt (V(t) + rt V(t+1)), gt folded into the SoC weights
     int32_t iv;    // lower speed cell of the successor (>= 0: infeasible pairs are dropped)
     int32_t dtc;   // whole time cells advanced
     int32_t u;     // control index a * n_m + b

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(1024) k_stage_sort(StageBase B)
         e.fv = (float)fv;
         e.gv = (float)(1.0 - fv);
         e.ft = (float)ft;
-        e.gt = (float)(1.0 - ft);
+        e.rt = (float)(ft / (1.0 - ft));   // ft < 1, so finite
         e.iv = c;
         e.dtc = dtc;
         e.u = u;
@@ -161,21 +161,24 @@ __global__ void __launch_bounds__(256) k_stage_rank(StageBase B)
     }
 }
 
-// Dwords of one packed record: the sorted entry (c, fv, gv, ft, gt, iv, dtc,
+// Dwords of one packed record: the sorted entry (c, fv, gv, ft, rt, iv, dtc,
 // u), the tile header, the SoC cells of the tile's rows as int8 offsets from
-// the row (JT / 4 dwords), then the tile's (fx, gx) pairs.
+// the row (JT / 4 dwords), then the tile's (fx gt, gx gt) pairs.
 __host__ __device__ constexpr int rec_cells(int JT) { return 9; }
 __host__ __device__ constexpr int rec_weights(int JT) { return 9 + JT / 4; }
 __host__ __device__ constexpr int rec_words(int JT) { return 9 + JT / 4 + 2 * JT; }
 // Cell offset of a row without a feasible successor (or past the tile).
 constexpr int kNoCell = -128;
+// Record header (dword 8): the window row (0 .. 2H) of the first successor
+// cell of a regular record, or one of these.
+constexpr int kRecIrregular = -1;   // rows read one by one
+constexpr int kRecEmpty = -2;       // no row of the tile has a successor
 
 // Battery coordinates of one (speed node, SoC tile, sorted position), written
 // as one packed record per (speed node, tile, position) so that the sweep
 // stages a run of controls with one contiguous copy: per SoC node the lower
-// cell (as an offset from the node) and the weights (fx, gx); the header is
-// the first node's cell when the tile's cells are consecutive (jx0 + q), else
-// -1.  One lane per (record, SoC row): the JT lanes of a
+// cell (as an offset from the node) and the weights (fx, gx) times gt; the
+// header says how the sweep reads the record.  One lane per (record, SoC row): the JT lanes of a
 // record are consecutive and aligned (JT divides the wave), consecutive
 // records are consecutive in memory, and the battery power and time step of
 // the control come from the sort (no second powertrain evaluation).
@@ -204,9 +207,15 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
     const int jc = min(JT, P.n_s - j0);
     int jx = -1;
     double fx = 0.0;
+    const double2 pd = pw[ir];
+    // the time weight gt of the control, exactly as the sort derived it
+    double gt;
+    {
+        const double delta = pd.y / P.ht;
+        gt = 1.0 - (delta - floor(delta));
+    }
     if (q < jc) {
         const int j = j0 + q;
-        const double2 pd = pw[ir];
         double I;
         const double xi = P.s_lo + j * P.hs;
         if (battery_current(P, pd.x, xi, I)) {
@@ -214,32 +223,71 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
             if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
         }
     }
-    // consecutive cells across the record's rows q < jc
+    // The record is regular when the tile is whole and its feasible rows
+    // have consecutive cells jx = b + q with |b - j0| <= H: the sweep then
+    // reads rows b .. b + JT from the staged window, whose LDS row 0 is SoC
+    // row j0 - H (possibly below the grid).  Rows without a successor read
+    // whatever those LDS rows hold and carry not-a-number weights, so their
+    // candidate never wins a comparison.
     const int lane = threadIdx.x & 63;
     const int base = lane & ~(JT - 1);
-    const int jx0 = __shfl(jx, base);
-    const bool ok = q >= jc || (jx >= 0 && jx == jx0 + q);
-    const unsigned long long bad = __ballot(!ok);
     const unsigned long long grp = (JT == 64 ? ~0ull : ((1ull << JT) - 1ull)) << base;
-    const bool regular = (bad & grp) == 0;
+    const unsigned long long feas = __ballot(jx >= 0) & grp;
+    const int first = feas ? __ffsll((long long)feas) - 1 : base;
+    const int b = __shfl(jx - q, first);
+    const unsigned long long bad = __ballot(jx >= 0 && jx - q != b) & grp;
+    int hdr = kRecIrregular;
+    if (feas == 0) hdr = kRecEmpty;
+    else if (bad == 0 && jc == JT && b >= j0 - jb.H && b <= j0 + jb.H) hdr = b - (j0 - jb.H);
     const int CW = rec_words(JT);
     float *out = rec + (((long)i * ntiles + tile) * P.n_u + r) * CW;
     const int WO = rec_weights(JT);
-    out[WO + 2 * q] = jx >= 0 ? (float)fx : 0.0f;
-    out[WO + 2 * q + 1] = jx >= 0 ? (float)(1.0 - fx) : 0.0f;
+    // SoC weights times the time weight gt (rounded once, from FP64)
+    const float nan = __int_as_float(0x7fc00000);
+    out[WO + 2 * q] = jx >= 0 ? (float)(fx * gt) : nan;
+    out[WO + 2 * q + 1] = jx >= 0 ? (float)((1.0 - fx) * gt) : nan;
     // the row's cell as a byte offset from the row (|offset| <= H + 1 < 127)
     reinterpret_cast<int8_t *>(out + rec_cells(JT))[q] = (int8_t)(jx >= 0 ? jx - (j0 + q) : kNoCell);
     const float *ef = reinterpret_cast<const float *>(&st[ir]);
-    for (int w = q; w < 9; w += JT) out[w] = w < 8 ? ef[w] : __int_as_float(regular ? jx0 : -1);
+    for (int w = q; w < 9; w += JT) out[w] = w < 8 ? ef[w] : __int_as_float(hdr);
 }
 
 // ------------------------------------------------------------------ sweep --
 
-__device__ inline float shl1(float x)
+// Time lerp of R rows at once, in place: T[q] += rt * T[q] of the next lane
+// (lane 63 adds 0), one v_fmac_f32_dpp per row (the compiler splits this into
+// a DPP move and an FMA).  A DPP read of a VGPR needs two wait states after
+// the VALU write of it: the leading s_nop covers the rows' last writes, and
+// inside the block every instruction reads only its own row.  The whole wave
+// must be active.
+#define ECODP_TL(i) "v_fmac_f32_dpp %" #i ", %" #i ", %[rt] wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+template <int R> __device__ inline void time_lerp(float (&T)[R], float rt);
+template <> __device__ inline void time_lerp<2>(float (&T)[2], float rt)
 {
-    // lane l receives lane l+1 (wave-wide shift); lane 63 receives 0
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, true));
+    asm("s_nop 1\n\t" ECODP_TL(0) ECODP_TL(1) : "+v"(T[0]), "+v"(T[1]) : [rt] "v"(rt));
 }
+template <> __device__ inline void time_lerp<5>(float (&T)[5], float rt)
+{
+    asm("s_nop 1\n\t" ECODP_TL(0) ECODP_TL(1) ECODP_TL(2) ECODP_TL(3) ECODP_TL(4)
+        : "+v"(T[0]), "+v"(T[1]), "+v"(T[2]), "+v"(T[3]), "+v"(T[4]) : [rt] "v"(rt));
+}
+template <> __device__ inline void time_lerp<9>(float (&T)[9], float rt)
+{
+    asm("s_nop 1\n\t" ECODP_TL(0) ECODP_TL(1) ECODP_TL(2) ECODP_TL(3) ECODP_TL(4) ECODP_TL(5) ECODP_TL(6)
+        ECODP_TL(7) ECODP_TL(8)
+        : "+v"(T[0]), "+v"(T[1]), "+v"(T[2]), "+v"(T[3]), "+v"(T[4]), "+v"(T[5]), "+v"(T[6]), "+v"(T[7]),
+          "+v"(T[8]) : [rt] "v"(rt));
+}
+template <> __device__ inline void time_lerp<17>(float (&T)[17], float rt)
+{
+    asm("s_nop 1\n\t" ECODP_TL(0) ECODP_TL(1) ECODP_TL(2) ECODP_TL(3) ECODP_TL(4) ECODP_TL(5) ECODP_TL(6)
+        ECODP_TL(7) ECODP_TL(8) ECODP_TL(9) ECODP_TL(10) ECODP_TL(11) ECODP_TL(12) ECODP_TL(13) ECODP_TL(14)
+        ECODP_TL(15) ECODP_TL(16)
+        : "+v"(T[0]), "+v"(T[1]), "+v"(T[2]), "+v"(T[3]), "+v"(T[4]), "+v"(T[5]), "+v"(T[6]), "+v"(T[7]),
+          "+v"(T[8]), "+v"(T[9]), "+v"(T[10]), "+v"(T[11]), "+v"(T[12]), "+v"(T[13]), "+v"(T[14]),
+          "+v"(T[15]), "+v"(T[16]) : [rt] "v"(rt));
+}
+#undef ECODP_TL
 
 // Registers per thread that prefetch the next run of control records.
 constexpr int kPrefetch = 4;
@@ -340,9 +388,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     const int split = rem - tile * nsplit;
     const int j0 = tile * JT;
     const int jc = min(JT, ns - j0);
+    // SoC rows wlo..whi are staged; LDS row r of a plane holds SoC row
+    // j0 - H + r (rows below 0 or above n_s - 1 are never staged)
     const int wlo = max(0, j0 - H);
     const int whi = min(ns - 1, j0 + jc + H);
     const int nrows = whi - wlo + 1;
+    const int wbase = j0 - H;
+    const int sh = wlo - wbase;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = wave * 63 + lane;
     const bool out_lane = lane < 63 && m < nt;
@@ -394,6 +446,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
         for (int cr = 0; cr < cn; cr++) {
             const float *ce = chunk + cr * CW;
             const int p = __builtin_amdgcn_readfirstlane(__float_as_int(ce[5]));
+            const int hdr = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
+            if (hdr == kRecEmpty) continue;          // no row of this tile has a successor
             if (p != cur_p) {
                 // stage planes p and p+1 (SoC rows wlo..whi, every time node),
                 // keeping a plane already resident from the previous group
@@ -417,11 +471,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                     // columns past the last time node hold a huge finite value:
                     // a candidate whose successor time leaves the grid (or sits
                     // on the last node with a positive fraction) is then far
-                    // above J_inf, while 0 x huge stays exact for a zero
-                    // fraction on the last node
+                    // above J_inf, infinite, or not a number (a zero SoC
+                    // weight times an infinite time lerp), none of which wins,
+                    // while 0 x huge stays exact for a zero fraction on the
+                    // last node
                     for (int rr = 0; rr < nrows; rr++) {
-                        if (need_p) lds[sp * slot_sz + rr * PITCH + t] = kPad;
-                        if (need_q) lds[sq * slot_sz + rr * PITCH + t] = kPad;
+                        if (need_p) lds[sp * slot_sz + (rr + sh) * PITCH + t] = kPad;
+                        if (need_q) lds[sq * slot_sz + (rr + sh) * PITCH + t] = kPad;
                     }
                 }
                 if (t < nt) {
@@ -438,8 +494,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
 #pragma unroll
                         for (int q = 0; q < kStageRows; q++) {
                             if (r0 + q < nrows) {
-                                if (need_p) lds[sp * slot_sz + (r0 + q) * PITCH + t] = va[q];
-                                if (need_q) lds[sq * slot_sz + (r0 + q) * PITCH + t] = vb[q];
+                                if (need_p) lds[sp * slot_sz + (r0 + q + sh) * PITCH + t] = va[q];
+                                if (need_q) lds[sq * slot_sz + (r0 + q + sh) * PITCH + t] = vb[q];
                             }
                         }
                     }
@@ -451,28 +507,25 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                 cur_p = p;
                 __syncthreads();
             }
-            const float c0f = ce[0], fv = ce[1], gv = ce[2], ft = ce[3], gt = ce[4];
+            const float c0f = ce[0], fv = ce[1], gv = ce[2], ft = ce[3], rt = ce[4];
             const int dtc = __float_as_int(ce[6]);
             const int u = __float_as_int(ce[7]);
-            const int jx0 = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
             const int pos = m + dtc;
-            const bool regular = jx0 >= wlo && jx0 + jc <= whi;
             const float *wp = ce + rec_weights(JT);
             float Qv[JT];
-            if (regular && jc == JT) {
+            if (hdr >= 0) {
                 // successor times past the grid read the padding columns
                 const int posc = min(pos, PITCH - 1);
                 const float c = c0f;
-                const int a0 = SA + (jx0 - wlo) * PITCH + posc;
-                const int b0 = SB + (jx0 - wlo) * PITCH + posc;
-                // speed lerp on the JT+1 SoC rows, then the time lerp with the
-                // neighbouring lane, then the SoC lerp per node
-                float V[JT + 1];
-#pragma unroll
-                for (int q = 0; q <= JT; q++) V[q] = fmaf(fv, lds[b0 + q * PITCH], gv * lds[a0 + q * PITCH]);
+                const int a0 = SA + hdr * PITCH + posc;
+                const int b0 = SB + hdr * PITCH + posc;
+                // speed lerp on the JT+1 SoC rows, then the time lerp with
+                // the neighbouring lane (scaled by 1/gt), then the SoC lerp
+                // per node (weights scaled by gt)
                 float T[JT + 1];
 #pragma unroll
-                for (int q = 0; q <= JT; q++) T[q] = fmaf(gt, V[q], ft * shl1(V[q]));
+                for (int q = 0; q <= JT; q++) T[q] = fmaf(fv, lds[b0 + q * PITCH], gv * lds[a0 + q * PITCH]);
+                time_lerp(T, rt);
 #pragma unroll
                 for (int q = 0; q < JT; q++) Qv[q] = fmaf(wp[2 * q], T[q + 1], fmaf(wp[2 * q + 1], T[q], c));
             } else {
@@ -491,20 +544,19 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                     const int jx = q < jc && off != kNoCell ? j0 + q + off : -1;
                     Qv[q] = Jinf;
                     if (jx >= 0) {
-                        float V0, V1;
+                        float T2[2];
                         if (jx >= wlo && jx + 1 <= whi) {
-                            const int a = SA + (jx - wlo) * PITCH + posc;
-                            const int b = SB + (jx - wlo) * PITCH + posc;
-                            V0 = fmaf(fv, lds[b], gv * lds[a]);
-                            V1 = fmaf(fv, lds[b + PITCH], gv * lds[a + PITCH]);
+                            const int a = SA + (jx - wbase) * PITCH + posc;
+                            const int b = SB + (jx - wbase) * PITCH + posc;
+                            T2[0] = fmaf(fv, lds[b], gv * lds[a]);
+                            T2[1] = fmaf(fv, lds[b + PITCH], gv * lds[a + PITCH]);
                         } else {
                             const float *a = Jn + (long)p * SV + (long)jx * nt + posc;
-                            V0 = fmaf(fv, a[SV], gv * a[0]);
-                            V1 = fmaf(fv, a[SV + nt], gv * a[nt]);
+                            T2[0] = fmaf(fv, a[SV], gv * a[0]);
+                            T2[1] = fmaf(fv, a[SV + nt], gv * a[nt]);
                         }
-                        const float T0 = fmaf(gt, V0, ft * shl1(V0));
-                        const float T1 = fmaf(gt, V1, ft * shl1(V1));
-                        Qv[q] = fmaf(wp[2 * q], T1, fmaf(wp[2 * q + 1], T0, c));
+                        time_lerp(T2, rt);
+                        Qv[q] = fmaf(wp[2 * q], T2[1], fmaf(wp[2 * q + 1], T2[0], c));
                     }
                 }
             }
