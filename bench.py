@@ -6,10 +6,12 @@ backward recursion with stage tables, state sweeps, signal handling and the
 exact root step (dp_solve), the FP64 policy rollout (dp_rollout) and the
 fixed-policy adjoint (dp_adjoint).  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.  The batched workload times the
-256-instance solve alone (one HIP-graph replay per step).
+256-instance solve alone (one HIP-graph replay per step); the mpc workload
+times closed-loop receding-horizon steps along a long route (one horizon
+re-solve from the measured state per step).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
-                  [--workload realistic|large|plain|paper|batched] [--kernel K] [--tile T] [--split S]
+                  [--workload realistic|large|plain|paper|batched|mpc] [--kernel K] [--tile T] [--split S]
 """
 from __future__ import annotations
 
@@ -33,6 +35,9 @@ DESCR = {
     "paper": "paper_shape: 20 stages x 35x26x40 states x 23x30 controls, 1 signal",
     "batched": "batched_256: 256 heterogeneous solves, 50-200 stages, (41-101)x(21-41)x(61-201) states, "
                "(21-41)x(11-21) controls, one HIP graph per solve",
+    "mpc": "mpc_3km: closed-loop receding horizon along a 3 km route (300 stages, 8 signals); per step one "
+           "20-stage horizon of 35x26x40 states x 23x30 controls with its terminal cost from an offline "
+           "full-route DP, solved from the measured state, u_0* applied to the FP64 plant",
 }
 
 
@@ -94,6 +99,73 @@ def measured_traffic(workload, kernel_name, split):
     return float(m.group(1))
 
 
+def cpu_baseline_mpc(route, budget_s: float):
+    """The FP64 oracle solving horizon problems of the route (stage 0, 1, ...
+    from the route's start state, zero terminal table: the work does not
+    depend on the values) on all host threads until the budget is spent."""
+    import numpy as np
+    import oracle
+    from paper_2104_01284_amd import instances
+    cores = oracle.num_threads()
+    t0 = time.perf_counter()
+    done = evals = 0
+    while True:
+        w = instances.mpc_window(route, done, 0.0, route["v0"], route["soc0"])
+        w["terminal_V"] = np.zeros((w["v_grid"][2], w["soc_grid"][2], w["t_grid"][2]))
+        oracle.solve(w)
+        done += 1
+        evals += instances.evaluations(w)
+        if time.perf_counter() - t0 >= budget_s or done >= route["N"]:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "state-control evals/s", "cores": cores, "kind": "oracle",
+            "ms_per_horizon": dt * 1e3 / done,
+            "sample": f"{done} horizon solves (stages 0..{done - 1} of {route['name']}), FP64, "
+                      f"{evals:.3e} evaluations in {dt:.1f} s on {cores} threads"}
+
+
+def bench_mpc(args):
+    """Closed-loop receding horizon: ``warmup`` untimed steps from the route
+    start, then ``steps`` timed steps of a fresh loop from the route start."""
+    import torch
+    from paper_2104_01284_amd import instances
+    from paper_2104_01284_amd.mpc import ClosedLoop
+    route = instances.mpc_route()
+    print(f"[bench] workload {DESCR['mpc']}", file=sys.stderr, flush=True)
+    if args.warmup:
+        ClosedLoop(route).run(args.warmup)
+    loop = ClosedLoop(route, plan_kw={"timing": True})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = loop.run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = len(res["steps"])
+    achieved = FLOPS_PER_EVAL * res["evals"] / (res["sweep_ms"] * 1e-3) / 1e12 if res["sweep_ms"] else None
+    out = {
+        "metric": "state-control evals/s and full-horizon solve ms (FP32 vs FP64 oracle, 1e-4 rel V_0)",
+        "value": res["evals"] / wall, "unit": "state-control evals/s",
+        "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": wall * 1e3 / max(1, k),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": DESCR["mpc"], "route_stages": int(route["N"]), "horizon": instances.MPC_HORIZON,
+                   "step": "signal wait + horizon build + terminal table + dp_solve + dp_rollout + D2H of the "
+                           "next state"},
+        "mpc": {"latency_ms": res["latency_ms"], "fuel_g": res["fuel_g"], "trip_s": res["t_abs"],
+                "cost": res["cost"], "wait_s": res["wait_s"], "violations": res["violations"],
+                "status": res["status"], "stages_driven": res["stage"], "offline_full_route_ms": res["offline_ms"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS if achieved else None, "traffic": None,
+                     "kernel": "state sweep", "avg_launch_ms": res["sweep_ms"] / max(1, res["sweep_launches"]),
+                     "launches": res["sweep_launches"]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_mpc(route, args.cpu_budget)
+        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,7 +187,8 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"plain": 1000, "paper": 200, "realistic": 50, "batched": 10, "large": 5}[args.workload]
+        args.steps = {"plain": 1000, "paper": 200, "realistic": 50, "batched": 10, "large": 5,
+                      "mpc": 300}[args.workload]
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
               f"run with --gpus 1", file=sys.stderr)
@@ -139,6 +212,9 @@ def main():
         print(json.dumps({"copy_calibration_MiB": args.copy_calibration, "copies": 3,
                           "expected_fetch_KiB_per_copy": args.copy_calibration * 1024,
                           "expected_write_KiB_per_copy": args.copy_calibration * 1024}))
+        return
+    if args.workload == "mpc":
+        bench_mpc(args)
         return
     batched = args.workload == "batched"
     insts = instances.batched(256) if batched else [instances.make(args.workload)]

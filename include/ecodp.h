@@ -61,6 +61,9 @@ enum {
 
 /* dp_problem_desc.flags */
 #define DP_WAIT_AT_RED 1u      /* a stopped vehicle at a red signal waits for green (Eq. 5c) */
+#define DP_TERMINAL_DEVICE 2u  /* terminal_V is a device pointer, copied device to device at
+                                  dp_build_problem on the null stream (work that wrote it on a
+                                  blocking stream has finished by then); else a host pointer */
 
 /* dp_options.flags */
 #define DP_STORE_ALL_V 1u      /* keep J_0..J_N (needed by dp_adjoint and for inspection) */
@@ -91,8 +94,9 @@ typedef struct {
     double konst[16];          /* g, rho_air, r_w, i_g, eta_dl, eta_m, C_nom [C], Voc0, Voc1 [V],
                                   R [ohm], a_min, a_max [m/s^2], xi_ref, J_inf, 0, 0               */
     double fuel[6];            /* fuel rate q0 + q1 v + q2 T + q3 v^2 + q4 v T + q5 T^2 [g/s], T > 0 */
-    const float *terminal_V;   /* optional [n_v][n_soc][n_t] added to the terminal cost; NULL = none */
-    uint32_t flags;            /* DP_WAIT_AT_RED */
+    const float *terminal_V;   /* optional [n_v][n_soc][n_t] added to the terminal cost; NULL = none
+                                  (host memory, or device memory with DP_TERMINAL_DEVICE)          */
+    uint32_t flags;            /* DP_WAIT_AT_RED, DP_TERMINAL_DEVICE */
 } dp_problem_desc;
 
 typedef struct {
@@ -167,6 +171,24 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
  * the SoC grid, all finite, else DP_EINVAL with nothing changed.  The stored
  * values and policy are stale afterwards (dp_adjoint needs a new dp_solve). */
 int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs, void *stream);
+
+/* Closed-loop receding horizon (Sec. III after Eq. 9, Sec. V): the terminal
+ * cost of a horizon is taken from the value function of an offline DP over
+ * the whole route.  This builds the terminal table of a horizon that starts
+ * at clock t_shift of that longer solve, from one of its value slabs:
+ * src: device float [n_v][n_soc][n_t_src] on the time grid [0, t_f_src];
+ * dst: device float [n_v][n_soc][n_t_dst] on the time grid [0, t_f_dst], the
+ * speed and SoC grids shared.  Node m of dst is the linear interpolation in
+ * time of src at t = t_shift + m t_f_dst / (n_t_dst - 1), computed in FP64
+ * and rounded once to FP32, capped at J_inf; a t past t_f_src gives J_inf.
+ * Pass dst as terminal_V (with DP_TERMINAL_DEVICE and w_soc = 0) of the
+ * horizon's problem.  n_v, n_soc >= 1, n_t_src, n_t_dst >= 2, t_f_src,
+ * t_f_dst > 0, t_shift >= 0, J_inf > 0, all finite, pointers non-NULL, else
+ * DP_EINVAL.  Enqueued on `stream`; src and dst must not overlap; the caller
+ * owns both. */
+int dp_terminal_from_values(const float *src, int32_t n_v, int32_t n_soc, int32_t n_t_src,
+                            double t_f_src, double t_shift, int32_t n_t_dst, double t_f_dst,
+                            double J_inf, float *dst, void *stream);
 
 /* Forward rollout of the stored policy from x0 with exact FP64 dynamics.
  * traj_dev: double rows [v, xi, t, u, T_eng, T_mot, fuel_g, cost] for stages

@@ -263,6 +263,90 @@ def adjoint(inst, J, pi, u0, want_rho=False):
     return out
 
 
+def window_terminal(J_slab, t_f_src, t_shift, n_t, t_f, J_inf):
+    """Terminal cost of a horizon that starts at clock ``t_shift`` of a longer
+    solve (Sec. III after Eq. 9: the value function of an offline full-route
+    DP serves as the horizon's terminal cost).  ``J_slab`` [n_v, n_s, n_src]
+    is that solve's value at the horizon's last stage on the time grid
+    [0, t_f_src]; the result [n_v, n_s, n_t] on [0, t_f] is the piecewise-linear
+    interpolation in time at t_shift + m t_f / (n_t - 1), J_inf past
+    t_f_src, capped at J_inf.  Plain FP64."""
+    J = np.asarray(J_slab, dtype=np.float64)
+    n_src = J.shape[2]
+    h_src = t_f_src / (n_src - 1)
+    h = t_f / (n_t - 1)
+    out = np.full(J.shape[:2] + (n_t,), float(J_inf))
+    for m in range(n_t):
+        r = (t_shift + m * h) / h_src
+        if r > n_src - 1:
+            continue
+        c = min(int(np.floor(r)), n_src - 2)
+        f = r - c
+        out[:, :, m] = np.minimum((1.0 - f) * J[:, :, c] + f * J[:, :, c + 1], J_inf)
+    return out
+
+
+def red_wait(inst_route, stage, t_abs):
+    """Wait of a vehicle stopped at the stop line of a red signal at ``stage``
+    until the end of red (Eq. 5c, Eq. 8); 0 if there is no signal or it is
+    green."""
+    for (L, Cy, R, O) in inst_route["lights"]:
+        if L == stage:
+            ph = (t_abs - O) % Cy
+            return R - ph if ph < R else 0.0
+    return 0.0
+
+
+def closed_loop(route, steps, horizon, t_f, n_t, window):
+    """The receding-horizon controller of Sec. V on ``route``: an offline
+    full-route DP gives the terminal cost; at every stage s the horizon
+    problem (``window(route, s, t_abs, v, soc)``, from the instance
+    generators) is solved with that terminal cost, its first control u_0* is
+    applied to the FP64 plant model (the same one-step model, Eq. 1-2, 5a-b),
+    the vehicle moves one step, and a vehicle stopped at a red signal first
+    waits for green.  Returns per step (s, t_abs, v, soc, V0, u0, q2 at the
+    root) and the trip totals."""
+    full = solve(route)
+    Jfull = full["J"]
+    t_f_src = route["t_grid"][1]
+    J_inf = route["konst"][13]
+    wt = route["theta"][3]
+    s, t_abs, v, soc = 0, route["t0_abs"], route["v0"], route["soc0"]
+    fuel = cost = 0.0
+    rows = []
+    status = 0
+    for _ in range(steps):
+        if s >= route["N"]:
+            break
+        if v == 0.0:
+            tau = red_wait(route, s, t_abs)
+            t_abs += tau
+            cost += wt * tau
+        win = window(route, s, t_abs, v, soc, horizon, t_f, n_t)
+        N = win["N"]
+        win["terminal_V"] = window_terminal(Jfull[s + N], t_f_src, t_abs - route["t0_abs"], n_t, t_f, J_inf)
+        I = Instance(win)
+        r = solve(I)
+        V0, u0, q2 = root(I, r["J"][1])
+        rows.append({"s": s, "t_abs": t_abs, "v": v, "soc": soc, "V0": V0, "u0": u0, "q2": q2})
+        if u0 < 0:
+            status = -4
+            break
+        a, b = divmod(u0, int(win["tm_grid"][2]))
+        st, o = transition(I, 0, v, soc, a, b)
+        if st & (4 | 8):      # the vehicle cannot move, or no battery current exists
+            status = -4
+            break
+        fuel += o["mf"] * o["dt"]
+        cost += o["cost"]
+        soc = soc - o["dt"] * o["I_bat"] / route["konst"][6]
+        v = o["v1"]
+        t_abs += o["dt"]
+        s += 1
+    return {"steps": rows, "fuel": fuel, "cost": cost, "t_abs": t_abs, "stage": s, "v": v, "soc": soc,
+            "status": status}
+
+
 def count_evals(inst):
     return int(_load().or_count_evals(_as_inst(inst).ref))
 

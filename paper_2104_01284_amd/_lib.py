@@ -14,13 +14,14 @@ SO_PATH = os.path.join(HERE, "libecodp.so")
 
 DP_OK, DP_EINVAL, DP_ENOMEM, DP_EDEVICE, DP_EINFEASIBLE, DP_ESTATE, DP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 DP_WAIT_AT_RED = 1
+DP_TERMINAL_DEVICE = 2
 DP_STORE_ALL_V = 1
 DP_TIMING = 2
 DP_GRAPH = 4
 
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_stage",
-           "dp_set_state", "dp_rollout", "dp_adjoint", "dp_sweep_time", "dp_destroy", "dp_status_string",
-           "dp_last_error")
+           "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_sweep_time", "dp_destroy",
+           "dp_status_string", "dp_last_error")
 
 
 class DpProblemDesc(C.Structure):
@@ -76,6 +77,8 @@ def load(require_torch: bool = True):
     lib.dp_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dp_stage.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
     lib.dp_set_state.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, vp]
+    lib.dp_terminal_from_values.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                            C.c_int32, C.c_double, C.c_double, vp, vp]
     lib.dp_rollout.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.dp_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dp_sweep_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]

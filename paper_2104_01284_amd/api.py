@@ -31,7 +31,16 @@ class _Desc:
         self.lr = np.array([x[2] for x in lights], dtype=np.float64)
         self.lo = np.array([x[3] for x in lights], dtype=np.float64)
         tv = inst.get("terminal_V")
-        self.term = None if tv is None else np.ascontiguousarray(tv, dtype=np.float32).ravel()
+        self.term_dev = None
+        self.term = None
+        if tv is not None and getattr(tv, "is_cuda", False):
+            # a device table (e.g. from terminal_from_values): copied device to device at build
+            import torch
+            if tv.dtype != torch.float32 or not tv.is_contiguous():
+                raise ValueError("a device terminal_V must be a contiguous float32 tensor")
+            self.term_dev = tv
+        elif tv is not None:
+            self.term = np.ascontiguousarray(tv, dtype=np.float32).ravel()
         d = L.DpProblemDesc()
         d.n_stages = N
         d.ds = inst["ds"]
@@ -56,9 +65,32 @@ class _Desc:
             d.konst[q] = x
         for q in range(6):
             d.fuel[q] = inst["fuel"][q]
-        d.terminal_V = None if self.term is None else self.term.ctypes.data_as(C.POINTER(C.c_float))
         d.flags = int(inst.get("flags", L.DP_WAIT_AT_RED))
+        if self.term_dev is not None:
+            d.terminal_V = C.cast(C.c_void_p(self.term_dev.data_ptr()), C.POINTER(C.c_float))
+            d.flags |= L.DP_TERMINAL_DEVICE
+        else:
+            d.terminal_V = None if self.term is None else self.term.ctypes.data_as(C.POINTER(C.c_float))
         self.d = d
+
+
+def terminal_from_values(src, t_f_src: float, t_shift: float, n_t: int, t_f: float, J_inf: float):
+    """Terminal table of a horizon starting at clock t_shift of a longer solve
+    (dp_terminal_from_values): src is a device float32 value slab
+    [n_v, n_soc, n_t_src] on the time grid [0, t_f_src]; returns a new device
+    float32 tensor [n_v, n_soc, n_t] on [0, t_f], enqueued on the current
+    stream.  Pass it as the horizon's terminal_V (with w_soc = 0)."""
+    import torch
+    if not (src.is_cuda and src.dtype == torch.float32 and src.dim() == 3 and src.is_contiguous()):
+        raise ValueError("src must be a contiguous float32 CUDA tensor [n_v, n_soc, n_t_src]")
+    n_v, n_s, n_src = src.shape
+    dst = torch.empty((n_v, n_s, int(n_t)), dtype=torch.float32, device=src.device)
+    lib = L.load()
+    stream = C.c_void_p(torch.cuda.current_stream(src.device).cuda_stream)
+    L.check(lib.dp_terminal_from_values(C.c_void_p(src.data_ptr()), n_v, n_s, n_src, float(t_f_src), float(t_shift),
+                                        int(n_t), float(t_f), float(J_inf), C.c_void_p(dst.data_ptr()), stream),
+            "dp_terminal_from_values")
+    return dst
 
 
 class Plan:

@@ -186,7 +186,16 @@ int validate(const dp_problem_desc &d, int b)
     if (d.n_t > 1024) return fail(DP_EUNSUPPORTED, "instance %d: n_t > 1024", b);
     if ((long)d.n_v * d.n_soc * d.n_t > (1L << 30))
         return fail(DP_EUNSUPPORTED, "instance %d: more than 2^30 states per stage (grid too large)", b);
-    if (d.flags & ~DP_WAIT_AT_RED) return fail(DP_EINVAL, "instance %d: unknown flags", b);
+    if (d.flags & ~(DP_WAIT_AT_RED | DP_TERMINAL_DEVICE)) return fail(DP_EINVAL, "instance %d: unknown flags", b);
+    if (d.flags & DP_TERMINAL_DEVICE) {
+        if (!d.terminal_V) return fail(DP_EINVAL, "instance %d: DP_TERMINAL_DEVICE without terminal_V", b);
+        hipPointerAttribute_t a;
+        if (hipPointerGetAttributes(&a, d.terminal_V) != hipSuccess ||
+            (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)) {
+            (void)hipGetLastError();
+            return fail(DP_EINVAL, "instance %d: DP_TERMINAL_DEVICE but terminal_V is not device memory", b);
+        }
+    }
     return DP_OK;
 }
 
@@ -571,6 +580,19 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         off += align_up(bytes, 256);
         return d;
     };
+    // device-resident terminal tables, copied after the host block
+    struct DevCopy {
+        char *dst;
+        const void *src;
+        size_t bytes;
+    };
+    std::vector<DevCopy> dev_copies;
+    auto put_device = [&](const void *src, size_t bytes) -> char * {
+        char *d = dev + off;
+        dev_copies.push_back({d, src, bytes});
+        off += align_up(bytes, 256);
+        return d;
+    };
     size_t J_off = 0, pi_off = 0, traj_off = 0, scr = 0;
     for (int b = 0; b < n_inst; b++) {
         const dp_problem_desc &d = desc[b];
@@ -641,7 +663,9 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         P.l_red = P.l_cycle + nl;
         P.l_off = P.l_red + nl;
         P.light_of_stage = (const int *)put(I.light_of_stage.data(), sizeof(int) * (N + 1));
-        P.terminal_V = d.terminal_V ? (const float *)put(d.terminal_V, sizeof(float) * I.S) : nullptr;
+        P.terminal_V = !d.terminal_V ? nullptr
+                       : (const float *)((d.flags & DP_TERMINAL_DEVICE) ? put_device(d.terminal_V, sizeof(float) * I.S)
+                                                                       : put(d.terminal_V, sizeof(float) * I.S));
         // the stage tables of k depend on k only through the grade of step k
         // and the speed limits at k and k+1
         I.same_tables.assign(N, 0);
@@ -757,6 +781,13 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         (void)hipFree(p->dev_params);
         delete p;
         return hip_fail(e, "parameter upload");
+    }
+    for (const DevCopy &c : dev_copies) {
+        if ((e = hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice)) != hipSuccess) {
+            (void)hipFree(p->dev_params);
+            delete p;
+            return hip_fail(e, "terminal table copy");
+        }
     }
     int rc = plan_rounds(p, scr);
     if (rc) {
@@ -1107,6 +1138,25 @@ int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs
     if (e != hipSuccess) return hip_fail(e, "state upload");
     p->state_pending = true;
     p->solved = false;
+    return DP_OK;
+}
+
+int dp_terminal_from_values(const float *src, int32_t n_v, int32_t n_soc, int32_t n_t_src, double t_f_src,
+                            double t_shift, int32_t n_t_dst, double t_f_dst, double J_inf, float *dst, void *stream)
+{
+    if (!src || !dst) return fail(DP_EINVAL, "terminal table: NULL pointer");
+    if (n_v < 1 || n_soc < 1 || n_t_src < 2 || n_t_dst < 2)
+        return fail(DP_EINVAL, "terminal table: grid sizes n_v=%d n_soc=%d n_t=%d/%d", n_v, n_soc, n_t_src, n_t_dst);
+    if (!(std::isfinite(t_f_src) && t_f_src > 0.0 && std::isfinite(t_f_dst) && t_f_dst > 0.0 &&
+          std::isfinite(t_shift) && t_shift >= 0.0 && std::isfinite(J_inf) && J_inf > 0.0))
+        return fail(DP_EINVAL, "terminal table: time grids, shift or J_inf out of range");
+    const long nvs = (long)n_v * n_soc;
+    const char *s0 = (const char *)src, *s1 = s0 + sizeof(float) * nvs * n_t_src;
+    const char *d0 = (const char *)dst, *d1 = d0 + sizeof(float) * nvs * n_t_dst;
+    if (s0 < d1 && d0 < s1) return fail(DP_EINVAL, "terminal table: src and dst overlap");
+    if (launch_terminal_shift(src, nvs, n_t_src, t_f_src / (n_t_src - 1), t_shift, n_t_dst, t_f_dst / (n_t_dst - 1),
+                              J_inf, dst, (hipStream_t)stream))
+        return hip_fail(hipGetLastError(), "terminal table launch");
     return DP_OK;
 }
 

@@ -29,6 +29,43 @@ __global__ void k_terminal(DevInst P, float *__restrict__ JN)
     }
 }
 
+// Terminal table of a horizon starting at clock t_shift of a longer solve
+// (Sec. III after Eq. 9): per node, the linear interpolation in time of that
+// solve's value slab, FP64 with one FP32 rounding, capped at J_inf.
+__global__ void k_terminal_shift(const float *__restrict__ src, long nvs, int n_src, double h_src, double t_shift,
+                                 int n_dst, double h_dst, double Jinf, float *__restrict__ dst)
+{
+#pragma clang fp contract(off)
+    const long S = nvs * n_dst;
+    for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
+        const int m = (int)(n % n_dst);
+        const long ij = n / n_dst;
+        const double t = t_shift + m * h_dst;
+        const double r = t / h_src;
+        double val = Jinf;
+        if (r <= (double)(n_src - 1)) {
+            int c = (int)floor(r);
+            if (c > n_src - 2) c = n_src - 2;
+            const double f = r - c;
+            const float *row = src + ij * n_src;
+            val = (1.0 - f) * (double)row[c] + f * (double)row[c + 1];
+            if (!(val < Jinf)) val = Jinf;
+        }
+        dst[n] = (float)val;
+    }
+}
+
+int launch_terminal_shift(const float *src, long nvs, int n_src, double h_src, double t_shift, int n_dst, double h_dst,
+                          double Jinf, float *dst, hipStream_t s)
+{
+    long blocks = (nvs * n_dst + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_terminal_shift, dim3((unsigned)blocks), dim3(256), 0, s, src, nvs, n_src, h_src, t_shift,
+                       n_dst, h_dst, Jinf, dst);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ------------------------------------------------------------- stage table --
 
 // One thread per (speed node i, control u, SoC node j), j fastest.  The

@@ -232,6 +232,62 @@ WORKLOADS = {
 }
 
 
+# Horizon of the closed-loop controller on the paper's own grid (Sec. IV):
+# 20 steps of 10 m, t_f = 80 s over 40 time nodes.
+MPC_HORIZON = 20
+MPC_T_F = 80.0
+MPC_N_T = 40
+
+
+def mpc_route(seed: int = 8, length_m: float = 3000.0, n_lights: int = 8) -> dict:
+    """A long route for the closed-loop receding-horizon controller (Sec. V):
+    ``length_m`` at 10 m steps, ``n_lights`` signals, +-3 % piecewise grade,
+    speed limits {25, 20, 15} m/s.  Its grids are those of the paper-shaped
+    horizon (35 speed x 26 SoC nodes, 23 x 30 controls); its time grid spans
+    the whole trip [0, 3.5 s per 10 m] with the horizon's time step, so that the
+    offline full-route DP that supplies the horizons' terminal cost (Sec. III
+    after Eq. 9) lives on the same state grid."""
+    rng = np.random.default_rng(seed)
+    N = int(round(length_m / 10.0))
+    grade, vmax, lights = _route(rng, N, n_lights, 25.0)
+    h_t = MPC_T_F / (MPC_N_T - 1)
+    n_t = int(np.ceil(3.5 * N / h_t)) + 1
+    if n_t > 1024:
+        raise ValueError("route too long for a 1024-node trip time grid")
+    return _base("mpc_route", seed, N, 10.0, grade, vmax, lights, 0.0, 0.0, 0.55,
+                 (0.0, 25.0, 35), (0.3, 0.8, 26), (0.0, h_t * (n_t - 1), n_t),
+                 (0.0, 150.0, 23), (-100.0, 100.0, 30), THETA0, draw_fuel(rng))
+
+
+def mpc_window(route: dict, s: int, t_abs: float, v: float, soc: float, horizon: int = MPC_HORIZON,
+               t_f: float = MPC_T_F, n_t: int = MPC_N_T) -> dict:
+    """The horizon problem of the closed loop at stage ``s`` of ``route``
+    (Eq. 6 with the window s .. s+N): the next N = min(horizon, N_route - s)
+    steps of the route's grade, speed limits and signals (signals strictly
+    inside the window, re-indexed from s), the current state (v, soc) at
+    absolute clock ``t_abs``, the horizon time grid [0, t_f] x n_t, and
+    w_soc = 0: the terminal cost comes in as ``terminal_V``, taken from the
+    full-route solve (the caller fills it)."""
+    N = min(int(horizon), int(route["N"]) - int(s))
+    if N < 1:
+        raise ValueError("no steps left on the route")
+    out = copy.deepcopy({k: v_ for k, v_ in route.items() if k != "terminal_V"})
+    out["name"] = f"{route['name']}@{s}"
+    out["N"] = N
+    out["grade"] = np.array(route["grade"][s:s + N], dtype=np.float64)
+    out["vmax"] = np.array(route["vmax"][s:s + N + 1], dtype=np.float64)
+    out["lights"] = [(L - s, C, R, O) for (L, C, R, O) in route["lights"] if s < L < s + N]
+    out["t0_abs"] = float(t_abs)
+    out["v0"] = float(v)
+    out["soc0"] = float(soc)
+    out["t_grid"] = (0.0, float(t_f), int(n_t))
+    theta = list(route["theta"])
+    theta[4] = 0.0
+    out["theta"] = theta
+    out["terminal_V"] = None
+    return out
+
+
 def make(name: str, **kw) -> dict:
     return WORKLOADS[name](**kw)
 

@@ -137,3 +137,43 @@ def test_per_instance_options_validated(lib):
     h = C.c_void_p()
     assert lib.dp_build_problem(arr, 2, C.byref(opt), 0, C.byref(h)) == L.DP_EINVAL
     assert "instance 1" in last_error(lib) and "tile[0]" in last_error(lib)
+
+
+def test_terminal_from_values_validated_before_device(lib):
+    """dp_terminal_from_values rejects bad grids, shifts, J_inf, NULL and
+    overlapping buffers on the host, before any launch."""
+    buf = (C.c_float * 64)()
+    other = (C.c_float * 64)()
+    src, dst = C.cast(buf, C.c_void_p), C.cast(other, C.c_void_p)
+    f = lib.dp_terminal_from_values
+    ok = dict(n_v=2, n_soc=2, n_t_src=4, t_f_src=10.0, t_shift=0.0, n_t_dst=3, t_f_dst=5.0, J_inf=1e4)
+
+    def call(s=src, d=dst, **kw):
+        a = dict(ok, **kw)
+        return f(s, a["n_v"], a["n_soc"], a["n_t_src"], a["t_f_src"], a["t_shift"], a["n_t_dst"], a["t_f_dst"],
+                 a["J_inf"], d, None)
+    assert call(s=None) == L.DP_EINVAL
+    assert call(d=None) == L.DP_EINVAL
+    assert call(n_t_src=1) == L.DP_EINVAL
+    assert call(n_t_dst=1) == L.DP_EINVAL
+    assert call(n_v=0) == L.DP_EINVAL
+    assert call(t_shift=-1.0) == L.DP_EINVAL
+    assert call(t_f_src=float("nan")) == L.DP_EINVAL
+    assert call(t_f_dst=0.0) == L.DP_EINVAL
+    assert call(J_inf=0.0) == L.DP_EINVAL
+    assert call(d=C.c_void_p(src.value + 8)) == L.DP_EINVAL     # overlapping
+    msg = C.create_string_buffer(256)
+    lib.dp_last_error(msg, 256)
+    assert b"overlap" in msg.value
+
+
+def test_device_terminal_flag_needs_device_memory(lib):
+    inst = ins.plain()
+    inst["terminal_V"] = np.zeros((21, 11, 31), dtype=np.float32)
+    d = _Desc(inst)
+    d.d.flags |= L.DP_TERMINAL_DEVICE                       # a host pointer with the device flag
+    h = C.c_void_p()
+    rc = lib.dp_build_problem(C.byref(d.d), 1, None, 0, C.byref(h))
+    assert rc in (L.DP_EINVAL, L.DP_EDEVICE)
+    d.d.terminal_V = None
+    assert lib.dp_build_problem(C.byref(d.d), 1, None, 0, C.byref(h)) == L.DP_EINVAL

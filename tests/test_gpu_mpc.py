@@ -94,3 +94,66 @@ def test_set_state_rejects_outside_grid(torch):
     with pytest.raises(L.DPError):
         plan.set_state(0, float("nan"), 0.5, 0.0)
     assert plan.lib.dp_set_state(plan._h, 3, 5.0, 0.5, 0.0, None) == L.DP_EINVAL
+
+
+# ------------------------------------------------- closed loop (Sec. V) --
+
+def test_terminal_from_values_matches_oracle(torch):
+    """The horizon's terminal table from a full-route value slab (Sec. III
+    after Eq. 9): the kernel against the oracle's interpolation on the same
+    seeded FP32 slab, exactly after the one FP32 rounding."""
+    from paper_2104_01284_amd.api import terminal_from_values
+    rng = np.random.default_rng(77)
+    n_v, n_s, n_src, t_f_src = 35, 26, 104, 211.3
+    J = rng.uniform(0.0, 300.0, (n_v, n_s, n_src)).astype(np.float32)
+    J[rng.random(J.shape) < 0.05] = 1.0e4          # some infeasible nodes
+    for shift in (0.0, 37.7, 150.0, 230.0):
+        say("terminal shift", shift)
+        dev = terminal_from_values(torch.from_numpy(J).cuda(), t_f_src, shift, 40, 80.0, 1.0e4)
+        torch.cuda.synchronize()
+        ref = oracle.window_terminal(J.astype(np.float64), t_f_src, shift, 40, 80.0, 1.0e4).astype(np.float32)
+        assert np.array_equal(dev.cpu().numpy(), ref), shift
+
+
+def test_device_terminal_equals_host_terminal(torch):
+    inst = ins.paper_shape()
+    rng = np.random.default_rng(78)
+    tv = rng.uniform(0.0, 40.0, (35, 26, 40)).astype(np.float32)
+    a = dict(inst, terminal_V=tv)
+    b = dict(inst, terminal_V=torch.from_numpy(tv).cuda())
+    pa, pb = Plan([a], store_all=True), Plan([b], store_all=True)
+    Va, _ = pa.solve()
+    Vb, _ = pb.solve()
+    torch.cuda.synchronize()
+    assert float(Va[0]) == float(Vb[0])
+    assert torch.equal(pa.values(0), pb.values(0)) and torch.equal(pa.policy(0), pb.policy(0))
+
+
+def test_closed_loop_matches_oracle(torch):
+    """Twelve steps of the receding-horizon controller on a 600 m route with
+    the paper's horizon grid: the GPU loop (FP32 values, FP64 plant) and the
+    oracle's loop (FP64 throughout), each with its own full-route DP for the
+    terminal cost.  Per step V_0 within 1e-4, the same u_0* (a differing
+    choice must be a near tie at the root, after which the loops may part),
+    and the plant states within 1e-9."""
+    from paper_2104_01284_amd.mpc import ClosedLoop
+    route = ins.mpc_route(seed=9, length_m=600.0, n_lights=2)
+    steps = 12
+    say("closed loop on", route["name"], "N", route["N"], "lights", route["lights"])
+    loop = ClosedLoop(route).run(steps)
+    ref = oracle.closed_loop(route, steps, ins.MPC_HORIZON, ins.MPC_T_F, ins.MPC_N_T, ins.mpc_window)
+    assert loop["status"] == 0 and ref["status"] == 0
+    for g, o in zip(loop["steps"], ref["steps"]):
+        assert g["s"] == o["s"]
+        for key in ("v", "soc", "t_abs"):
+            assert abs(g[key] - o[key]) <= 1e-9 * max(1.0, abs(o[key])), (g["s"], key, g[key], o[key])
+        assert abs(g["V0"] - o["V0"]) <= 1e-4 * abs(o["V0"]), (g["s"], g["V0"], o["V0"])
+        if g["u0"] != o["u0"]:
+            assert o["q2"] - o["V0"] < 1e-4 * max(1.0, abs(o["V0"])), (g["s"], g["u0"], o["u0"])
+            say("u0 differs at a near tie, stage", g["s"])
+            break
+    else:
+        assert len(loop["steps"]) == len(ref["steps"]) == steps
+        assert loop["fuel_g"] == pytest.approx(ref["fuel"], rel=1e-9)
+    lat = loop["latency_ms"]
+    say("latency ms mean %.3f max %.3f" % (lat["mean"], lat["max"]))
