@@ -298,6 +298,25 @@ def with_theta(inst: dict, theta) -> dict:
     return out
 
 
+def value_slab(inst: dict, seed: int) -> np.ndarray:
+    """A seeded stand-in for a next-stage value slab J_{k+1} [n_v, n_soc, n_t]
+    (FP32): a bowl in speed and SoC, a ramp in time, small noise, J_INF at the
+    latest 15 % of the time nodes and on one speed row.  Both the oracle and
+    the library can then be fed the same J_{k+1} for an isolated stage at any
+    grid size."""
+    rng = np.random.default_rng(seed)
+    n_v, n_s, n_t = inst["v_grid"][2], inst["soc_grid"][2], inst["t_grid"][2]
+    v = np.linspace(0.0, 1.0, n_v)[:, None, None]
+    x = np.linspace(0.0, 1.0, n_s)[None, :, None]
+    t = np.linspace(0.0, 1.0, n_t)[None, None, :]
+    a, bv, bs, ct = rng.uniform(20, 60), rng.uniform(10, 40), rng.uniform(50, 200), rng.uniform(5, 40)
+    v0, x0 = rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7)
+    J = a + bv * (v - v0) ** 2 + bs * (x - x0) ** 2 + ct * t + rng.uniform(0.0, 0.5, (n_v, n_s, n_t))
+    J[:, :, int(np.ceil(0.85 * n_t)):] = J_INF
+    J[int(rng.integers(0, n_v)), :, :] = J_INF
+    return J.astype(np.float32)
+
+
 def evaluations(inst: dict) -> int:
     """Dense state-control evaluations of one full backward sweep: every grid
     node of every stage 0..N-1 times every control pair (Sec. IV counts the

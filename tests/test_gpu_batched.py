@@ -184,8 +184,9 @@ def test_batched_members_against_oracle_and_single(torch):
 def test_full_batch_sampled(torch):
     """The full 256-instance batch in the launch configuration the benchmark
     times: every member against its single solve bit for bit (V_0, u_0*, J_0,
-    pi_0), and stage-0 nodes of a stratified subset (smallest, largest, every
-    16th) against the oracle fed the GPU's own J_1."""
+    pi_0), and stage 0 of a stratified subset (smallest, largest, every 16th)
+    in the batch's configuration from seeded J_1 slabs, on sampled nodes
+    against the oracle fed the same slab."""
     insts = ins.batched(256)
     say("full batch: 256 instances")
     big = Plan(insts, store_all=False, graph=True)
@@ -207,9 +208,11 @@ def test_full_batch_sampled(torch):
         inst = insts[b]
         I = oracle.Instance(inst)
         shp = big.slab_shape(b)
-        J1 = big.value(b, 1).cpu().numpy()
-        J0 = big.value(b, 0).cpu().numpy().astype(np.float64)
-        p0 = big.policy(b, 0).cpu().numpy()
+        # stage 0 of the member in the batch's configuration from a seeded J_1
+        J1 = ins.value_slab(inst, 5000 + b)
+        J0, p0 = big.stage(b, 0, torch.from_numpy(J1).cuda())
+        torch.cuda.synchronize()
+        J0, p0 = J0.cpu().numpy().astype(np.float64), p0.cpu().numpy()
         J1_64 = J1.astype(np.float64).ravel()
         say("member", b, inst["name"], "shape", shp, "N", inst["N"])
         for _ in range(40):

@@ -69,16 +69,20 @@ def test_set_state_equals_fresh_plan(torch, case, graph):
 
 
 def test_rollout_follows_moved_state(torch):
+    """After dp_set_state the rollout starts from the moved state: with the
+    oracle's solve of the moved instance loaded into the plan, the GPU
+    rollout equals the oracle's."""
     inst = ins.plain()
     plan = Plan([inst], store_all=True)
     plan.solve()
     plan.set_state(0, 8.2, 0.52, 11.0)
     plan.solve()
+    r = oracle.solve(moved(inst, 8.2, 0.52, 11.0))
+    plan.policy(0).copy_(torch.from_numpy(r["pi"]).cuda())
+    plan.u0.fill_(int(r["u0"]))
     trajs, status = plan.rollout()
     torch.cuda.synchronize()
-    pi = plan.policy(0).cpu().numpy()
-    u0 = int(plan.u0.cpu()[0])
-    ro = oracle.rollout(moved(inst, 8.2, 0.52, 11.0), pi, u0)
+    ro = oracle.rollout(moved(inst, 8.2, 0.52, 11.0), r["pi"], r["u0"])
     st = status.cpu().numpy()[0]
     assert st[0] == ro["status"] and st[1] == ro["violations"]
     tg = trajs[0].cpu().numpy()

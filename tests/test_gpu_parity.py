@@ -9,8 +9,8 @@ Tolerances (FP32 values, FP64 coordinates):
     1e-6 gap is below its resolution for J > 16 g; the count under the
     absolute reading is reported too).
   * Terminal slab: exactly the FP32 rounding of the FP64 value.
-  * Rollout (same policy): FP64 agreement to 1e-9 relative.
-  * Adjoint (same J and policy): FP64 agreement to 1e-9 relative.
+  * Rollout (the oracle's policy loaded into the plan): FP64 agreement to 1e-9 relative.
+  * Adjoint (the oracle's FP32-rounded J and policy loaded): FP64 agreement to 1e-9 relative.
 """
 import json
 import os
@@ -136,16 +136,26 @@ def test_ragged_and_edge_instances(torch, idx, kernel):
         check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), inst["name"])
 
 
-def test_rollout_matches_oracle_given_gpu_policy(torch):
+def load_oracle_solution(torch, plan, inst, r):
+    """Put the oracle's own solve (values rounded to FP32, policy, u_0*) into
+    the plan's buffers, so that the GPU rollout and adjoint run on inputs
+    that come from the oracle."""
+    plan.values(0).copy_(torch.from_numpy(r["J"].astype(np.float32)).cuda())
+    plan.policy(0).copy_(torch.from_numpy(r["pi"]).cuda())
+    plan.u0.fill_(int(r["u0"]))
+    torch.cuda.synchronize()
+
+
+def test_rollout_matches_oracle_given_oracle_policy(torch):
     for inst in [ins.plain()] + ragged_instances()[:1]:
         say("rollout", inst["name"])
+        r = oracle.solve(inst)
         plan = Plan([inst], store_all=True)
         plan.solve()
+        load_oracle_solution(torch, plan, inst, r)
         trajs, status = plan.rollout()
         torch.cuda.synchronize()
-        pi = plan.policy(0).cpu().numpy()
-        u0 = int(plan.u0.cpu()[0])
-        ro = oracle.rollout(inst, pi, u0)
+        ro = oracle.rollout(inst, r["pi"], r["u0"])
         st = status.cpu().numpy()[0]
         assert st[0] == ro["status"] and st[1] == ro["violations"]
         tg = trajs[0].cpu().numpy()
@@ -155,20 +165,39 @@ def test_rollout_matches_oracle_given_gpu_policy(torch):
         np.testing.assert_allclose(tg[both], to[both], rtol=1e-9, atol=1e-9)
 
 
-def test_adjoint_matches_oracle_given_gpu_values(torch):
+def test_adjoint_matches_oracle_given_oracle_values(torch):
     for inst in [ins.plain()] + ragged_instances()[:1]:
         say("adjoint", inst["name"])
+        r = oracle.solve(inst)
         plan = Plan([inst], store_all=True)
         plan.solve()
+        load_oracle_solution(torch, plan, inst, r)
         g = plan.adjoint()
         torch.cuda.synchronize()
-        J = plan.values(0).cpu().numpy().astype(np.float64)
-        pi = plan.policy(0).cpu().numpy()
-        u0 = int(plan.u0.cpu()[0])
-        go = oracle.adjoint(inst, J, pi, u0)["grad"]
-        gt = oracle.tangent(inst, J, pi, u0)
+        J32 = r["J"].astype(np.float32).astype(np.float64)
+        go = oracle.adjoint(inst, J32, r["pi"], r["u0"])["grad"]
+        gt = oracle.tangent(inst, J32, r["pi"], r["u0"])
         np.testing.assert_allclose(g.cpu().numpy()[0], go, rtol=1e-9, atol=1e-12)
         np.testing.assert_allclose(go, gt, rtol=1e-9, atol=1e-12)
+
+
+def sampled_isolated(torch, plan, inst, k, seed, samples, rng):
+    """Stage k in the plan's launch configuration from a seeded J_{k+1}
+    (the same slab on both sides), compared with the oracle on sampled
+    nodes."""
+    Jn = ins.value_slab(inst, seed)
+    Jg, pg = plan.stage(0, k, torch.from_numpy(Jn).cuda())
+    torch.cuda.synchronize()
+    Jg, pg = Jg.cpu().numpy().astype(np.float64), pg.cpu().numpy()
+    I = oracle.Instance(inst)
+    Jn64 = Jn.astype(np.float64).ravel()
+    shp = Jn.shape
+    for _ in range(samples):
+        i, j, m = (int(rng.integers(0, n)) for n in shp)
+        Jo, po, q2 = oracle.node(I, k, Jn64, i, j, m)
+        assert abs(Jg[i, j, m] - Jo) <= REL_J * max(1.0, abs(Jo)), (k, i, j, m, Jg[i, j, m], Jo)
+        if pg[i, j, m] != po:
+            assert q2 - Jo < REL_GAP * max(1.0, abs(Jo)), (k, i, j, m, pg[i, j, m], po, q2 - Jo)
 
 
 def test_autograd_function(torch):
@@ -229,33 +258,23 @@ def test_realistic_against_golden(torch):
 
 
 def test_realistic_sampled_isolated_stages(torch):
-    """Full-size launch configuration: the GPU's own J_{k+1} fed to both the
-    GPU step and the oracle, compared on sampled nodes."""
+    """Full-size launch configuration: a seeded J_{k+1} fed to both the GPU
+    step and the oracle, compared on sampled nodes."""
     inst = ins.realistic()
     plan = Plan([inst], store_all=True)
     plan.solve()
     torch.cuda.synchronize()
     rng = np.random.default_rng(9)
-    I = oracle.Instance(inst)
     for k in (0, 42, 43, 120, 199):
         say("realistic_2km sampled stage", k)
-        Jn = plan.values(0)[k + 1].cpu().numpy()
-        Jg = plan.values(0)[k].cpu().numpy().astype(np.float64)
-        pg = plan.policy(0, k).cpu().numpy()
-        Jn64 = Jn.astype(np.float64).ravel()
-        for _ in range(200):
-            i, j, m = int(rng.integers(0, 101)), int(rng.integers(0, 41)), int(rng.integers(0, 201))
-            Jo, po, q2 = oracle.node(I, k, Jn64, i, j, m)
-            assert abs(Jg[i, j, m] - Jo) <= REL_J * max(1.0, abs(Jo)), (k, i, j, m, Jg[i, j, m], Jo)
-            if pg[i, j, m] != po:
-                assert q2 - Jo < REL_GAP * max(1.0, abs(Jo)), (k, i, j, m, pg[i, j, m], po, q2 - Jo)
+        sampled_isolated(torch, plan, inst, k, 1000 + k, 200, rng)
 
 
 def test_large_last_stages_and_sampled_isolated(torch):
     """The 3 km instance (300 stages, 201x81x401 states) in the benchmark's
     launch configuration: the last five stages on the full grid against the
     oracle's own recursion from J_N, and sampled nodes of stages 0, 150 and
-    298 against the oracle fed the GPU's J_{k+1}."""
+    298 from seeded J_{k+1} slabs."""
     inst = ins.large()
     N = inst["N"]
     plan = Plan([inst], store_all=True)
@@ -275,18 +294,9 @@ def test_large_last_stages_and_sampled_isolated(torch):
         say("max relative J error", float(err.max()))
         assert err.max() < 1e-4, (k, float(err.max()))
     rng = np.random.default_rng(5)
-    shp = plan.slab_shape(0)
     for k in (0, 150, 298):
         say("large_3km sampled isolated stage", k)
-        Jn = plan.values(0)[k + 1].cpu().numpy().astype(np.float64).ravel()
-        Jg = plan.values(0)[k].cpu().numpy().astype(np.float64)
-        pg = plan.policy(0, k).cpu().numpy()
-        for _ in range(150):
-            i, j, m = (int(rng.integers(0, n)) for n in shp)
-            Jo_n, po, q2 = oracle.node(I, k, Jn, i, j, m)
-            assert abs(Jg[i, j, m] - Jo_n) <= REL_J * max(1.0, abs(Jo_n)), (k, i, j, m, Jg[i, j, m], Jo_n)
-            if pg[i, j, m] != po:
-                assert q2 - Jo_n < REL_GAP * max(1.0, abs(Jo_n)), (k, i, j, m, pg[i, j, m], po)
+        sampled_isolated(torch, plan, inst, k, 2000 + k, 150, rng)
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
