@@ -92,7 +92,10 @@ typedef struct {
     double tm_lo, tm_hi; int32_t n_tm;   /* BSG torque grid [Nm], n_tm >= 1                         */
     double theta[5];           /* M [kg], CdA [m^2], Crr, w_t [g/s], w_soc [g]                     */
     double konst[16];          /* g, rho_air, r_w, i_g, eta_dl, eta_m, C_nom [C], Voc0, Voc1 [V],
-                                  R [ohm], a_min, a_max [m/s^2], xi_ref, J_inf, 0, 0               */
+                                  R [ohm], a_min, a_max [m/s^2], xi_ref, J_inf, P_eng_max [W],
+                                  P_bsg_max [W]: the speed-dependent torque limits of Eq. 7e-f as
+                                  T_eng <= P_eng_max / omega(v), |T_bsg| <= P_bsg_max / omega(v) at
+                                  the crank speed omega of the step's initial speed (0 = no cap) */
     double fuel[6];            /* fuel rate q0 + q1 v + q2 T + q3 v^2 + q4 v T + q5 T^2 [g/s], T > 0 */
     const float *terminal_V;   /* optional [n_v][n_soc][n_t] added to the terminal cost; NULL = none
                                   (host memory, or device memory with DP_TERMINAL_DEVICE)          */

@@ -40,6 +40,8 @@ static double grid_val(double lo, double hi, int n, int i) { return lo + i * gri
 #define K_AMAX 11
 #define K_XIREF 12
 #define K_JINF 13
+#define K_PENG 14   /* engine power cap [W], 0 = none (Eq. 7e as T_eng <= P/omega(v)) */
+#define K_PBSG 15   /* BSG power cap [W], 0 = none (Eq. 7f as |T_bsg| <= P/omega(v)) */
 
 #define T_M 0
 #define T_CDA 1
@@ -111,6 +113,10 @@ static void powertrain(const or_inst *I, int k, double v, int a, int b, pt_t *p)
     const double w = v * K[K_IG] / K[K_RW];
     const double Pm = Tm * w;
     p->Pb = Pm >= 0.0 ? Pm / K[K_ETAM] : Pm * K[K_ETAM];
+    /* Eq. 7e-f: speed-dependent torque limits, here the torque a power cap
+     * allows at the crank speed of the step's initial speed */
+    if (K[K_PENG] > 0.0 && Te * w > K[K_PENG]) p->st |= 16;
+    if (K[K_PBSG] > 0.0 && fabs(Tm) * w > K[K_PBSG]) p->st |= 16;
 }
 
 /* Zeroth-order equivalent circuit: P_bat = Voc*I - R*I^2, Voc linear in SoC.

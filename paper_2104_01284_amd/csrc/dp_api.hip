@@ -177,7 +177,8 @@ int validate(const dp_problem_desc &d, int b)
     for (int q = 0; q < 16; q++)
         if (!finite(d.konst[q])) return fail(DP_EINVAL, "instance %d: konst[%d] not finite", b, q);
     const double *K = d.konst;
-    if (!(K[2] > 0 && K[3] > 0 && K[4] > 0 && K[5] > 0 && K[6] > 0 && K[9] > 0 && K[13] > 0 && K[10] < K[11]))
+    if (!(K[2] > 0 && K[3] > 0 && K[4] > 0 && K[5] > 0 && K[6] > 0 && K[9] > 0 && K[13] > 0 && K[10] < K[11] &&
+          K[14] >= 0 && K[15] >= 0))
         return fail(DP_EINVAL, "instance %d: vehicle constants out of range", b);
     for (int q = 0; q < 6; q++)
         if (!finite(d.fuel[q])) return fail(DP_EINVAL, "instance %d: fuel[%d] not finite", b, q);
@@ -642,6 +643,8 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         P.amax = K[11];
         P.xiref = K[12];
         P.Jinf = K[13];
+        P.peng = K[14];
+        P.pbsg = K[15];
         for (int q = 0; q < 6; q++) P.q[q] = d.fuel[q];
         P.v0 = d.v0;
         P.soc0 = d.soc0;

@@ -22,6 +22,7 @@ struct DevInst {
     double e_lo, m_lo;
     double M, CdA, Crr, wt, wsoc;
     double g, rho, rw, ig, eta, etam, Cnom, Voc0, Voc1, Rb, amin, amax, xiref, Jinf;
+    double peng, pbsg;           // engine and BSG power caps [W] (Eq. 7e-f), 0 = none
     double q[6];
     double v0, soc0, t0_abs;
     const double *cosa, *sina;   // [N] grade trigonometry (host FP64)
@@ -113,7 +114,7 @@ struct StageBase {
 // Result of the continuous one-step model for (stage k, speed v, control).
 struct PT {
     double v1, acc, dt, cost, mf, Pb, q, Ftr, Froad, cosa, sina;
-    int st;        // 1 accel bound, 2 speed limit, 4 zero mean speed
+    int st;        // 1 accel bound, 2 speed limit, 4 zero mean speed, 16 torque limit
 };
 
 // Eq. 5a (constant force over the step), Eq. 2, Eq. 1 and the BSG power
@@ -157,6 +158,9 @@ __device__ __host__ inline PT powertrain(const DevInst &P, int k, double v, int 
     const double w = v * P.ig / P.rw;
     const double Pm = Tm * w;
     p.Pb = Pm >= 0.0 ? Pm / P.etam : Pm * P.etam;
+    // Eq. 7e-f: the torque a power cap allows at the step's initial crank speed
+    if (P.peng > 0.0 && Te * w > P.peng) p.st |= 16;
+    if (P.pbsg > 0.0 && fabs(Tm) * w > P.pbsg) p.st |= 16;
     return p;
 }
 

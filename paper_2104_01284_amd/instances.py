@@ -33,7 +33,8 @@ import copy
 import numpy as np
 
 KONST_NAMES = ("g", "rho_air", "r_w", "i_g", "eta_dl", "eta_m", "C_nom",
-               "Voc0", "Voc1", "R_bat", "a_min", "a_max", "xi_ref", "J_inf")
+               "Voc0", "Voc1", "R_bat", "a_min", "a_max", "xi_ref", "J_inf",
+               "P_eng_max", "P_bsg_max")
 
 # Cost given to infeasible states and state-control pairs: orders of magnitude
 # above a stage cost (about 1 g per 10 m step) and above any feasible total.
@@ -44,9 +45,11 @@ WAIT_AT_RED = 1  # option flag bit: a stopped vehicle may wait out a red phase (
 
 
 def default_konst(xi_ref: float) -> list:
-    """Vehicle/battery constants of the synthetic 48 V mild hybrid."""
+    """Vehicle/battery constants of the synthetic 48 V mild hybrid; the last
+    two are the engine and BSG power caps of the speed-dependent torque
+    limits (Eq. 7e-f), 0 = none."""
     return [9.81, 1.2, 0.30, 3.0, 0.95, 0.90, 28800.0, 42.0, 12.0, 0.1,
-            -2.5, 2.0, float(xi_ref), J_INF]
+            -2.5, 2.0, float(xi_ref), J_INF, 0.0, 0.0]
 
 
 def draw_fuel(rng: np.random.Generator) -> list:
@@ -286,6 +289,38 @@ def mpc_window(route: dict, s: int, t_abs: float, v: float, soc: float, horizon:
     out["theta"] = theta
     out["terminal_V"] = None
     return out
+
+
+def with_torque_limits(inst: dict, p_eng: float, p_bsg: float) -> dict:
+    """The instance with speed-dependent torque limits (Eq. 7e-f) given as
+    engine and BSG power caps [W]: T_eng <= p_eng / omega(v) and
+    |T_bsg| <= p_bsg / omega(v) at the crank speed of the step's initial
+    speed."""
+    out = copy.deepcopy(inst)
+    out["konst"] = list(out["konst"]) + [0.0] * (16 - len(out["konst"]))
+    out["konst"][14] = float(p_eng)
+    out["konst"][15] = float(p_bsg)
+    return out
+
+
+def with_stop_signs(inst: dict, stages) -> dict:
+    """The instance with stop signs at the given stages: the route speed
+    limit there is 0 (Eq. 7a), so the vehicle must be at rest at the sign."""
+    out = copy.deepcopy(inst)
+    vmax = np.array(out["vmax"], dtype=np.float64)
+    for k in stages:
+        if not 1 <= int(k) <= int(out["N"]) - 1:
+            raise ValueError("a stop sign must sit at a stage in [1, N-1]")
+        vmax[int(k)] = 0.0
+    out["vmax"] = vmax
+    out["stop_signs"] = [int(k) for k in stages]
+    return out
+
+
+def plain_fidelity(seed: int = 1) -> dict:
+    """The 500 m instance with a stop sign at 150 m and engine/BSG power caps
+    of 20 kW and 8 kW (the caps bind above about 13 m/s and 8 m/s)."""
+    return with_stop_signs(with_torque_limits(plain(seed), 20000.0, 8000.0), [15])
 
 
 def make(name: str, **kw) -> dict:

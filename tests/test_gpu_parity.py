@@ -316,3 +316,27 @@ def test_paper_shape_end_to_end_and_isolated(torch, kernel):
     assert err.max() < 1e-4, float(err.max())
     for k in range(inst["N"]):
         check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), "paper_shape")
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_fidelity_variants_end_to_end_and_isolated(torch, kernel):
+    """Stop sign (Eq. 7a with a zero limit) and speed-dependent torque limits
+    (Eq. 7e-f as power caps) on the 500 m instance: end-to-end V_0 and J and
+    every stage isolated against the oracle, for both sweep kernels; the
+    rollout rests at the sign."""
+    inst = ins.plain_fidelity()
+    say("plain_fidelity kernel", kernel)
+    r = oracle.solve(inst, q2=True)
+    plan = Plan([inst], store_all=True, kernel=kernel)
+    V0, u0 = plan.solve()
+    torch.cuda.synchronize()
+    assert abs(float(V0.cpu()[0]) - r["V0"]) <= 1e-4 * abs(r["V0"])
+    J = plan.values(0).cpu().numpy().astype(np.float64)
+    err = np.abs(J - r["J"]) / np.maximum(1.0, np.abs(r["J"]))
+    assert err.max() < 1e-4, float(err.max())
+    for k in range(inst["N"]):
+        check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), "plain_fidelity")
+    trajs, status = plan.rollout()
+    torch.cuda.synchronize()
+    k = inst["stop_signs"][0]
+    assert int(status.cpu()[0, 0]) == 0 and float(trajs[0][k, 0].cpu()) == 0.0
