@@ -209,6 +209,17 @@ int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_d
 int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
                void *scratch, double *grad_dev, void *stream);
 
+/* dp_adjoint plus the sensitivity of V_0 to the grade of every step (a
+ * route parameter per step, Eq. 5a through the road load): dgrade_dev: double
+ * [sum over instances of N], instance b at the offset of the N of the
+ * instances before it, dgrade[k] = dV_0/dG_k with the policy fixed.  G_k
+ * enters only the road load of step k, like C_rr, so dV_0/dG_k is
+ * cos a_k (cos a_k - C_rr sin a_k) times step k's share of dV_0/dC_rr; the
+ * shares are kept per step in the scratch buffer.  Not a number where x0 has
+ * no admissible control (as grad_dev). */
+int dp_adjoint_grade(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
+                     void *scratch, double *grad_dev, double *dgrade_dev, void *stream);
+
 /* With DP_TIMING: total device milliseconds and launch count of the state
  * sweep kernel over every dp_solve / dp_stage since the previous call
  * (synchronises on the recorded events, then starts a new count). */

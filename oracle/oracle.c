@@ -634,6 +634,25 @@ static void step_partials(const or_inst *I, const steps_t *h, double v, const pt
     }
 }
 
+/* Partial derivatives of the stage cost and of the successor's index
+ * coordinates with respect to the grade G of step k (control fixed): G enters
+ * only the road load F_road = M g (Crr cos a + sin a) with cos a =
+ * 1/sqrt(1 + G^2), sin a = G cos a, so dF_road/dG = M g cos^3 a (1 - Crr G). */
+static void grade_partials(const or_inst *I, const steps_t *h, int k, double v, const pt_t *p, double Ib,
+                           double *dc, double dr[3])
+{
+    const double M = I->theta[T_M], ds = I->ds, G = I->grade[k], c = p->cosa;
+    const double dFroad = M * I->konst[K_G] * c * c * c * (1.0 - I->theta[T_CRR] * G);
+    const double dq = -2.0 * ds * dFroad / M;
+    const double dv1 = p->q > 0.0 ? dq / (2.0 * p->v1) : 0.0;
+    const double vs = v + p->v1;
+    const double ddt = -2.0 * ds / (vs * vs) * dv1;
+    *dc = (p->mf + I->theta[T_WT]) * ddt;
+    dr[0] = dv1 / h->hv;
+    dr[1] = -(Ib / (I->konst[K_CNOM] * h->hs)) * ddt;
+    dr[2] = ddt / h->ht;
+}
+
 void or_tangent(const or_inst *I, const double *J_all, const int16_t *pi_all, int32_t u0, double grad[5])
 {
     const long S = slab_size(I);
@@ -733,7 +752,7 @@ static void scatter(const or_inst *I, double *rho_next, double rho, cf_t v, cf_t
 
 void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, int32_t u0,
                 double grad[5], double *rho_sum, double *absorbed, double *exp_cost, double *exp_time,
-                double *exp_socpen, double *rho_all)
+                double *exp_socpen, double *rho_all, double *dgrade)
 {
     const long S = slab_size(I);
     const steps_t h = steps_of(I);
@@ -748,6 +767,7 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
     if (absorbed) for (int k = 0; k <= I->N; k++) absorbed[k] = 0.0;
     if (exp_cost) for (int k = 0; k <= I->N; k++) exp_cost[k] = 0.0;
     if (rho_all) memset(rho_all, 0, sizeof(double) * S * (I->N + 1));
+    if (dgrade) for (int k = 0; k < I->N; k++) dgrade[k] = NAN;   /* like grad, when x0 has no control */
     if (u0 < 0) goto done;
     {
         /* the root step from x0 puts unit mass on the bracketing nodes of stage 1 */
@@ -762,6 +782,12 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
         step_partials(I, &h, I->v0, &p, sc.Ib, dc, dr);
         interp_grad(I, J_all + S, sc.v, sc.s, sc.t, gJ);
         for (int q = 0; q < 5; q++) g[q] += dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2];
+        if (dgrade) {
+            double dcg, drg[3];
+            grade_partials(I, &h, 0, I->v0, &p, sc.Ib, &dcg, drg);
+            for (int k = 0; k < I->N; k++) dgrade[k] = 0.0;
+            dgrade[0] = dcg + drg[0] * gJ[0] + drg[1] * gJ[1] + drg[2] * gJ[2];
+        }
         if (rho_sum) rho_sum[0] = 1.0;
         if (exp_cost) exp_cost[0] = p.cost;
         etime += p.dt;
@@ -804,6 +830,11 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
                         interp_grad(I, Jn, sc.v, sc.s, sc.t, gJ);
                         for (int q = 0; q < 5; q++)
                             g[q] += r * (dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2]);
+                        if (dgrade) {
+                            double dcg, drg[3];
+                            grade_partials(I, &h, k, v, &p, sc.Ib, &dcg, drg);
+                            dgrade[k] += r * (dcg + drg[0] * gJ[0] + drg[1] * gJ[1] + drg[2] * gJ[2]);
+                        }
                         etime += r * p.dt;
                         if (exp_cost) exp_cost[k] += r * p.cost;
                         scatter(I, rn, r, sc.v, sc.s, sc.t);

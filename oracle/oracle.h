@@ -93,7 +93,7 @@ void or_tangent(const or_inst *I, const double *J_all, const int16_t *pi_all, in
  * exp_socpen (expected terminal (xi - xi_ref)^2), rho_all [(N+1)*S]. */
 void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, int32_t u0,
                 double grad[5], double *rho_sum, double *absorbed, double *exp_cost, double *exp_time,
-                double *exp_socpen, double *rho_all);
+                double *exp_socpen, double *rho_all, double *dgrade);
 
 /* Evaluation counter of a full sweep (dense counting, Sec. IV). */
 int64_t or_count_evals(const or_inst *I);

@@ -246,6 +246,19 @@ class Plan:
                                     C.c_void_p(grad.data_ptr()), self._stream()), "dp_adjoint")
         return grad.view(self.n, 5)
 
+    def adjoint_grade(self):
+        """dV_0/dtheta (FP64 [n, 5]) and dV_0/dG_k for the grade of every step
+        (FP64, one [N_b] tensor per instance), the stored policy held fixed."""
+        torch = self.torch
+        grad = torch.empty(5 * self.n, dtype=torch.float64, device=self.V0.device)
+        Ns = [int(i.n_stages) for i in self.info]
+        dg = torch.empty(sum(Ns), dtype=torch.float64, device=self.V0.device)
+        L.check(self.lib.dp_adjoint_grade(self._h, C.c_void_p(self.J.data_ptr()), C.c_void_p(self.pi.data_ptr()),
+                                          C.c_void_p(self.u0.data_ptr()), C.c_void_p(self.scratch.data_ptr()),
+                                          C.c_void_p(grad.data_ptr()), C.c_void_p(dg.data_ptr()), self._stream()),
+                "dp_adjoint_grade")
+        return grad.view(self.n, 5), list(dg.split(Ns))
+
     def sweep_time(self):
         ms, n = C.c_double(), C.c_int32()
         L.check(self.lib.dp_sweep_time(self._h, C.byref(ms), C.byref(n)), "dp_sweep_time")

@@ -277,7 +277,7 @@ __device__ bool successor_cells(const DevInst &P, int k, double v, double xi, do
 }
 
 __global__ void k_adj_root(DevInst P, const float *__restrict__ J1, const int16_t *__restrict__ u0p,
-                           double *__restrict__ rho1, double *__restrict__ gacc)
+                           double *__restrict__ rho1, double *__restrict__ gacc, double *__restrict__ gstage)
 {
 #pragma clang fp contract(off)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -295,6 +295,8 @@ __global__ void k_adj_root(DevInst P, const float *__restrict__ J1, const int16_
     step_partials(P, P.v0, p, I, dc, dr);
     interp_grad(P, J1, x, gJ);
     for (int q = 0; q < 5; q++) gacc[q] += dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2];
+    // stage 0's share of dV/dC_rr (slot 0 of stage 0; the other slots stay 0)
+    if (gstage) gstage[0] = dc[2] + dr[2][0] * gJ[0] + dr[2][1] * gJ[1] + dr[2][2] * gJ[2];
     scatter(P, rho1, 1.0, x, false);
 }
 
@@ -303,8 +305,9 @@ __global__ void k_adj_root(DevInst P, const float *__restrict__ J1, const int16_
 constexpr int kAdjBlocks = 1024;
 
 // Sum g over the workgroup (wave shuffles, then one LDS step) and add it to
-// the workgroup's own slot gpart[blockIdx.x][0..4].
-__device__ inline void block_add5(double g[5], double *gpart)
+// the workgroup's own slot gpart[blockIdx.x][0..4]; with gcrr, also store
+// this launch's C_rr sum (component 2) in gcrr[blockIdx.x].
+__device__ inline void block_add5(double g[5], double *gpart, double *gcrr = nullptr)
 {
     __shared__ double red[16][5];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -318,6 +321,23 @@ __device__ inline void block_add5(double g[5], double *gpart)
         double x = 0.0;
         for (int ww = 0; ww < nw; ww++) x += red[ww][threadIdx.x];
         gpart[(long)blockIdx.x * 5 + threadIdx.x] += x;
+        if (gcrr && threadIdx.x == 2) gcrr[blockIdx.x] = x;
+    }
+}
+
+// dV/dG_k for every step k: the grade of step k enters only the road load,
+// like C_rr, with dF_road/dG = M g cos^3 a (1 - C_rr G) against dF_road/dC_rr
+// = M g cos a, so dV/dG_k is cos a (cos a - C_rr sin a) times step k's share
+// of dV/dC_rr (summed over the kAdjBlocks slots of gstage[k]).
+__global__ void __launch_bounds__(256) k_adj_grade(DevInst P, const double *__restrict__ gstage,
+                                                   const double *__restrict__ grad, double *__restrict__ dgrade)
+{
+#pragma clang fp contract(off)
+    const bool none = grad[0] != grad[0];   // x0 had no admissible control: not a number, like grad
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P.N; k += gridDim.x * blockDim.x) {
+        double x = 0.0;
+        for (int b = 0; b < kAdjBlocks; b++) x += gstage[(long)k * kAdjBlocks + b];
+        dgrade[k] = none ? grad[0] : P.cosa[k] * (P.cosa[k] - P.Crr * P.sina[k]) * x;
     }
 }
 
@@ -351,7 +371,7 @@ constexpr int kAdjChunk = 512;
 __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
                                                    const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
                                                    const double *__restrict__ rho, double *__restrict__ rho_next,
-                                                   double *__restrict__ gacc)
+                                                   double *__restrict__ gacc, double *__restrict__ gcrr)
 {
 #pragma clang fp contract(off)
     __shared__ int s_list[kAdjChunk];
@@ -404,7 +424,7 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
         }
         __syncthreads();   // the list is read before the next chunk rewrites it
     }
-    block_add5(g, gacc);
+    block_add5(g, gacc, gcrr);
 }
 
 // Stage N: dV/dw_soc gains rho_N (xi - xi_ref)^2 on nodes below J_inf.
@@ -458,17 +478,18 @@ int launch_adjoint_reduce(const double *gpart, double *grad, hipStream_t s)
 }
 
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
-                        hipStream_t s)
+                        double *gstage, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adj_root, dim3(1), dim3(64), 0, s, P, J1, u0, rho1, gacc);
+    hipLaunchKernelGGL(k_adj_root, dim3(1), dim3(64), 0, s, P, J1, u0, rho1, gacc, gstage);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
-                         const double *rho, double *rho_next, double *gacc, hipStream_t s)
+                         const double *rho, double *rho_next, double *gacc, double *gstage, hipStream_t s)
 {
     // kAdjBlocks workgroups walk the chunks, each adding into its own slot
-    hipLaunchKernelGGL(k_adj_stage, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc);
+    hipLaunchKernelGGL(k_adj_stage, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc,
+                       gstage ? gstage + (long)k * kAdjBlocks : nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -477,5 +498,13 @@ int launch_adjoint_terminal(const DevInst &P, const float *JN, const double *rho
     hipLaunchKernelGGL(k_adj_terminal, dim3(kAdjBlocks), dim3(256), 0, s, P, JN, rho, gacc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+int launch_adjoint_grade(const DevInst &P, const double *gstage, const double *grad, double *dgrade, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_grade, dim3((P.N + 255) / 256), dim3(256), 0, s, P, gstage, grad, dgrade);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+size_t adjoint_grade_slots() { return (size_t)kAdjBlocks; }
 
 }  // namespace ecodp

@@ -111,6 +111,7 @@ struct dp_plan {
     int *dev_ib = nullptr;
     size_t scr_q = 0;                // 8 queue counters per sweep launch, then 8 for dp_stage
     size_t scr_gpart = 0;            // adjoint partial gradient sums
+    size_t scr_gstage = 0;           // adjoint per-stage C_rr shares (grade sensitivities)
     int n_q_slots = 0;
     // independent sweep launches of a round run on these streams side by side
     static constexpr int kSide = 3;
@@ -461,6 +462,10 @@ static int plan_rounds(dp_plan *p, size_t scr)
     scr += align_up(sizeof(int) * 8 * (size_t)p->n_q_slots, 256);
     p->scr_gpart = scr;   // adjoint: per-workgroup partial gradient sums
     scr += align_up(sizeof(double) * 5 * 1024, 256);
+    int max_N = 1;
+    for (const Inst &I : p->inst) max_N = std::max(max_N, I.N);
+    p->scr_gstage = scr;  // adjoint: per-(stage, workgroup) C_rr shares for the grade sensitivities
+    scr += align_up(sizeof(double) * adjoint_grade_slots() * (size_t)max_N, 256);
     p->bytes_scratch = scr;
 
     const size_t b_inst = align_up(sizeof(DevInst) * n_inst, 256);
@@ -1179,8 +1184,8 @@ int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_d
     return DP_OK;
 }
 
-int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch, double *grad_dev,
-               void *stream)
+static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch,
+                        double *grad_dev, double *dgrade_dev, void *stream)
 {
     if (!p) return fail(DP_EINVAL, "plan is NULL");
     if (!(p->flags & DP_STORE_ALL_V)) return fail(DP_ESTATE, "adjoint needs a plan built with DP_STORE_ALL_V");
@@ -1189,8 +1194,10 @@ int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    size_t dgrade_off = 0;
     for (size_t b = 0; b < p->inst.size(); b++) {
         const Inst &I = p->inst[b];
+        double *gstage = dgrade_dev ? (double *)((char *)scratch + p->scr_gstage) : nullptr;
         double *rho_a = (double *)((char *)scratch + I.scr_rho);
         double *rho_b = rho_a + I.S;
         double *g = grad_dev + 5 * b;
@@ -1198,16 +1205,17 @@ int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
         const int16_t *pib = (const int16_t *)((const char *)pi + I.pi_off);
         double *gpart = (double *)((char *)scratch + p->scr_gpart);
         if (launch_fill_f64(g, 5, 0.0, s) || launch_fill_f64(rho_a, (long)I.S, 0.0, s) ||
-            launch_fill_f64(gpart, 5L * 1024, 0.0, s))
+            launch_fill_f64(gpart, 5L * 1024, 0.0, s) ||
+            (gstage && launch_fill_f64(gstage, (long)adjoint_grade_slots(), 0.0, s)))
             return hip_fail(hipGetLastError(), "fill launch");
-        if (launch_adjoint_root(I.P, Jb + I.S, u0_dev + b, rho_a, g, s))
+        if (launch_adjoint_root(I.P, Jb + I.S, u0_dev + b, rho_a, g, gstage, s))
             return hip_fail(hipGetLastError(), "adjoint root launch");
         for (int k = 1; k < I.N; k++) {
             const int L = I.light_of_stage[k];
             const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
             if (launch_fill_f64(rho_b, (long)I.S, 0.0, s)) return hip_fail(hipGetLastError(), "fill launch");
             if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, rho_a, rho_b, gpart,
-                                     s))
+                                     gstage, s))
                 return hip_fail(hipGetLastError(), "adjoint stage launch");
             double *t = rho_a;
             rho_a = rho_b;
@@ -1216,8 +1224,24 @@ int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
         if (launch_adjoint_terminal(I.P, Jb + (size_t)I.N * I.S, rho_a, gpart, s))
             return hip_fail(hipGetLastError(), "adjoint terminal launch");
         if (launch_adjoint_reduce(gpart, g, s)) return hip_fail(hipGetLastError(), "adjoint reduce launch");
+        if (gstage && launch_adjoint_grade(I.P, gstage, g, dgrade_dev + dgrade_off, s))
+            return hip_fail(hipGetLastError(), "adjoint grade launch");
+        dgrade_off += (size_t)I.N;
     }
     return DP_OK;
+}
+
+int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch, double *grad_dev,
+               void *stream)
+{
+    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, nullptr, stream);
+}
+
+int dp_adjoint_grade(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch,
+                     double *grad_dev, double *dgrade_dev, void *stream)
+{
+    if (!dgrade_dev) return fail(DP_EINVAL, "NULL grade-sensitivity buffer");
+    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, dgrade_dev, stream);
 }
 
 int dp_sweep_time(dp_plan *p, double *ms, int32_t *launches)

@@ -38,9 +38,11 @@ int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, doubl
                    hipStream_t s);
 int launch_fill_f64(double *p, long n, double v, hipStream_t s);
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
-                        hipStream_t s);
+                        double *gstage, hipStream_t s);
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
-                         const double *rho, double *rho_next, double *gacc, hipStream_t s);
+                         const double *rho, double *rho_next, double *gacc, double *gstage, hipStream_t s);
+int launch_adjoint_grade(const DevInst &P, const double *gstage, const double *grad, double *dgrade, hipStream_t s);
+size_t adjoint_grade_slots();
 // gpart: the adjoint kernels' per-workgroup partial gradient sums (1024 x 5
 // doubles, zeroed before the first stage); grad += their sum.
 int launch_adjoint_reduce(const double *gpart, double *grad, hipStream_t s);

@@ -340,3 +340,26 @@ def test_fidelity_variants_end_to_end_and_isolated(torch, kernel):
     torch.cuda.synchronize()
     k = inst["stop_signs"][0]
     assert int(status.cpu()[0, 0]) == 0 and float(trajs[0][k, 0].cpu()) == 0.0
+
+
+def test_grade_sensitivities_match_oracle(torch):
+    """dV_0/dG_k for every step (dp_adjoint_grade) on the oracle's own solve
+    loaded into the plan, against the oracle's adjoint on the same FP32-rounded
+    values: FP64 agreement to 1e-9; the theta gradient agrees with dp_adjoint's
+    to rounding."""
+    cases = [ins.plain(), ins.tiny(seed=401, N=12, n_v=11, n_s=7, n_t=41, n_e=5, n_m=5, light=True, t_f=60.0)]
+    for inst in cases:
+        say("grade sensitivities", inst["name"])
+        r = oracle.solve(inst)
+        plan = Plan([inst], store_all=True)
+        plan.solve()
+        load_oracle_solution(torch, plan, inst, r)
+        g5, dg = plan.adjoint_grade()
+        g_only = plan.adjoint()
+        torch.cuda.synchronize()
+        # the occupancy scatter adds with FP64 atomics, so two runs agree to rounding
+        np.testing.assert_allclose(g5.cpu().numpy(), g_only.cpu().numpy(), rtol=1e-12, atol=1e-15)
+        J32 = r["J"].astype(np.float32).astype(np.float64)
+        ao = oracle.adjoint(inst, J32, r["pi"], r["u0"])
+        np.testing.assert_allclose(dg[0].cpu().numpy(), ao["dgrade"], rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(g5.cpu().numpy()[0], ao["grad"], rtol=1e-9, atol=1e-12)

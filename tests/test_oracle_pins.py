@@ -7,6 +7,7 @@ enumeration on tiny problems written here independently, invariants of the
 recursion (signal constraint, lower bound, decoupling, occupancy), finite
 differences of fresh solves, and the workload arithmetic the paper states.
 """
+import copy
 import itertools
 import json
 import math
@@ -584,3 +585,47 @@ def test_single_node_matches_stage_sweep():
             i, j, m = (int(rng.integers(0, n)) for n in (21, 11, 31))
             J, pi, q2 = oracle.node(inst, k, r["J"][k + 1], i, j, m)
             assert J == r["J"][k, i, j, m] and pi == r["pi"][k, i, j, m] and q2 == r["q2"][k, i, j, m]
+
+
+def _grade_stable(inst, ks, h):
+    """Central difference of V_0 in the grade of the steps ``ks`` (all moved
+    together) from fresh solves, and whether the policy on the occupancy
+    support stays the same for the two perturbed solves."""
+    def moved(d):
+        x = copy.deepcopy(inst)
+        x["grade"] = np.array(x["grade"], dtype=np.float64)
+        x["grade"][list(ks)] += d
+        return x
+    sols = [oracle.solve(moved(d)) for d in (0.0, h, -h)]
+    ads = [oracle.adjoint(moved(d), r["J"], r["pi"], r["u0"], want_rho=True) for d, r in zip((0.0, h, -h), sols)]
+    supp = [(a["rho"] > 0) for a in ads]
+    stable = (sols[0]["u0"] == sols[1]["u0"] == sols[2]["u0"]
+              and all(np.array_equal(supp[0], s_) for s_ in supp[1:])
+              and all(np.array_equal(sols[0]["pi"][supp[0][:-1]], r["pi"][supp[0][:-1]]) for r in sols[1:]))
+    return stable, (sols[1]["V0"] - sols[2]["V0"]) / (2 * h)
+
+
+def test_grade_sensitivities_fd():
+    """dV_0/dG_k for every step k from the occupancy sweep: central
+    differences of fresh solves in one grade (and in all grades together,
+    whose derivative is the sum) agree at policy-stable points; on a flat
+    route the grade and rolling resistance enter the road load alike
+    (dF/dG = dF/dC_rr = M g), so the sum equals dV_0/dC_rr."""
+    small = copy.deepcopy(ins.plain())
+    for base in (small, ins.tiny(seed=401, N=12, n_v=11, n_s=7, n_t=41, n_e=5, n_m=5, light=True, t_f=60.0)):
+        r = oracle.solve(base)
+        ad = oracle.adjoint(base, r["J"], r["pi"], r["u0"])
+        dg = ad["dgrade"]
+        assert dg.shape == (base["N"],)
+        checked = 0
+        for ks in ([0], [base["N"] // 3], [base["N"] - 2], list(range(base["N"]))):
+            want = dg[ks].sum()
+            for h in (1e-4, 1e-5, 1e-6):
+                stable, fd = _grade_stable(base, ks, h)
+                if stable:
+                    assert fd == pytest.approx(want, rel=1e-5, abs=1e-9), (base["name"], ks, h, fd, want)
+                    checked += 1
+                    break
+        assert checked >= 3, base["name"]
+        if np.all(np.asarray(base["grade"]) == 0.0):
+            assert dg.sum() == pytest.approx(ad["grad"][2], rel=1e-12)
