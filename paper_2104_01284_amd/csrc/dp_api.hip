@@ -203,10 +203,9 @@ int validate(const dp_problem_desc &d, int b)
 
 double gstep(double lo, double hi, int n) { return n > 1 ? (hi - lo) / (n - 1) : 0.0; }
 
-// Signal table of one light: per time node, the red flag and the wait to
-// green (Eq. 5c) in index space; FP64 on the host.
 // Signal table of one light over the time grid [0, t_f] x n_t (Eq. 5c, 8):
-// red flag and, for a stopped vehicle, the wait to the end of red.
+// per time node the red flag and, for a stopped vehicle, the wait to the end
+// of red in index space; FP64 on the host.
 void build_tl(double C, double R, double O, double t0_abs, double t_f, int n_t, double wt, TLEntry *out)
 {
     const double ht = gstep(0.0, t_f, n_t);
