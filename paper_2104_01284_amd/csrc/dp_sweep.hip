@@ -223,12 +223,14 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
             if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
         }
     }
-    // The record is regular when the tile is whole and its feasible rows
-    // have consecutive cells jx = b + q with |b - j0| <= H: the sweep then
-    // reads rows b .. b + JT from the staged window, whose LDS row 0 is SoC
-    // row j0 - H (possibly below the grid).  Rows without a successor read
-    // whatever those LDS rows hold and carry not-a-number weights, so their
-    // candidate never wins a comparison.
+    // The record is regular when its feasible rows have consecutive cells
+    // jx = b + q with |b - j0| <= H and the tile holds at least half of JT
+    // rows: the sweep then reads rows b .. b + JT from the staged window,
+    // whose LDS row 0 is SoC row j0 - H (possibly below the grid), for all
+    // JT rows.  Rows without a successor, and rows past a short last tile,
+    // read whatever those LDS rows hold and carry not-a-number weights, so
+    // their candidate never wins a comparison.  (A tile of fewer rows is
+    // cheaper on the general path, which works row by row.)
     const int lane = threadIdx.x & 63;
     const int base = lane & ~(JT - 1);
     const unsigned long long grp = (JT == 64 ? ~0ull : ((1ull << JT) - 1ull)) << base;
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
     const unsigned long long bad = __ballot(jx >= 0 && jx - q != b) & grp;
     int hdr = kRecIrregular;
     if (feas == 0) hdr = kRecEmpty;
-    else if (bad == 0 && jc == JT && b >= j0 - jb.H && b <= j0 + jb.H) hdr = b - (j0 - jb.H);
+    else if (bad == 0 && 2 * jc >= JT && b >= j0 - jb.H && b <= j0 + jb.H) hdr = b - (j0 - jb.H);
     const int CW = rec_words(JT);
     float *out = rec + (((long)i * ntiles + tile) * P.n_u + r) * CW;
     const int WO = rec_weights(JT);
