@@ -322,7 +322,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     // stay in one L2); a job's speed nodes come in decreasing order of work,
     // which keeps a band's nodes close in speed and leaves the shortest items
     // for the end.  A workgroup whose band is drained takes items from the
-    // other bands; every workgroup exits once all queues are drained.
+    // other bands; every workgroup exits once all queues are drained.  A
+    // launch with no more items than workgroups skips the queues.
     __shared__ int s_item, s_job;
     const int home = blockIdx.x & 7;
     int qi = 0;
@@ -330,6 +331,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     for (;;) {
     if (threadIdx.x == 0) {
         int item = -1, job = 0;
+        if (total <= (int)gridDim.x) {
+            // no more items than workgroups: workgroup b takes item b and
+            // leaves (a drained queue polled by every workgroup would cost
+            // more than the work)
+            if (qi == 0 && (int)blockIdx.x < total) item = blockIdx.x;
+            qi = 8;
+        }
         while (qi < 8) {
             const int x = (home + qi) & 7;
             const int lo = (int)(((long)total * x) >> 3), hi = (int)(((long)total * (x + 1)) >> 3);

@@ -24,6 +24,7 @@ moves the state between steps and keeps the statistics.
 """
 from __future__ import annotations
 
+import gc
 import math
 import statistics
 import time
@@ -88,50 +89,58 @@ class ClosedLoop:
         sweep_ms, launches = 0.0, 0
         timing = bool(self.plan_kw.get("timing"))
         stream = torch.cuda.current_stream(self.device)
-        for _ in range(steps):
-            t_start = time.perf_counter()
-            if v == 0.0:
-                tau = _red_wait(r["lights"], s, t_abs)
-                t_abs += tau
-                wait_s += tau
-                cost += r["theta"][3] * tau
-            win = ins.mpc_window(r, s, t_abs, v, soc, self.horizon, self.t_f, self.n_t)
-            N = int(win["N"])
-            win["terminal_V"] = terminal_from_values(self.J_full[s + N], t_f_route, t_abs - float(r["t0_abs"]),
-                                                     self.n_t, self.t_f, J_inf)
-            stream.synchronize()                    # the plan copies the table at build
-            plan = Plan([win], device=self.device, **self.plan_kw)
-            V0, u0 = plan.solve()
-            traj, _ = plan.rollout()
-            # rows 0 and 1: the applied control and the plant step (the rollout's
-            # own status covers its whole open-loop horizon, of which only the
-            # first step is applied here)
-            head = traj[0][:2].cpu()
-            lat_ms = (time.perf_counter() - t_start) * 1e3
-            evals += ins.evaluations(win)
-            if timing:
-                ms, n = plan.sweep_time()
-                sweep_ms += ms
-                launches += n
-            V0h = float(V0.cpu()[0])
-            u = int(head[0, 3])
-            rows.append({"s": s, "t_abs": t_abs, "v": v, "soc": soc, "V0": V0h, "u0": u, "latency_ms": lat_ms})
-            v1, soc1, dt = float(head[1, 0]), float(head[1, 1]), float(head[1, 2])
-            if u < 0 or not (math.isfinite(v1) and math.isfinite(soc1) and math.isfinite(dt)):
-                status = -4                         # no admissible control from this state
-                break
-            fuel += float(head[1, 6])
-            cost += float(head[1, 7])
-            s += 1
-            v, soc, t_abs = v1, soc1, t_abs + dt
-            if s < N_route:
-                if v > float(r["vmax"][s]):
-                    violations += 1
-                if v > 0.0 and _red_wait(r["lights"], s, t_abs) > 0.0:
-                    violations += 1                 # crossing a signal during red
-            if not (s_lo <= soc <= s_hi):
-                status = -4
-                break
+        # a full garbage collection scans every object torch has created and
+        # takes tens of milliseconds: the existing heap leaves the
+        # collector's view for the loop, so a step pays only for its own objects
+        gc.collect()
+        gc.freeze()
+        try:
+            for _ in range(steps):
+                t_start = time.perf_counter()
+                if v == 0.0:
+                    tau = _red_wait(r["lights"], s, t_abs)
+                    t_abs += tau
+                    wait_s += tau
+                    cost += r["theta"][3] * tau
+                win = ins.mpc_window(r, s, t_abs, v, soc, self.horizon, self.t_f, self.n_t)
+                N = int(win["N"])
+                win["terminal_V"] = terminal_from_values(self.J_full[s + N], t_f_route, t_abs - float(r["t0_abs"]),
+                                                         self.n_t, self.t_f, J_inf)
+                stream.synchronize()                    # the plan copies the table at build
+                plan = Plan([win], device=self.device, **self.plan_kw)
+                V0, u0 = plan.solve()
+                traj, _ = plan.rollout()
+                # rows 0 and 1: the applied control and the plant step (the rollout's
+                # own status covers its whole open-loop horizon, of which only the
+                # first step is applied here)
+                head = traj[0][:2].cpu()
+                lat_ms = (time.perf_counter() - t_start) * 1e3
+                evals += ins.evaluations(win)
+                if timing:
+                    ms, n = plan.sweep_time()
+                    sweep_ms += ms
+                    launches += n
+                V0h = float(V0.cpu()[0])
+                u = int(head[0, 3])
+                rows.append({"s": s, "t_abs": t_abs, "v": v, "soc": soc, "V0": V0h, "u0": u, "latency_ms": lat_ms})
+                v1, soc1, dt = float(head[1, 0]), float(head[1, 1]), float(head[1, 2])
+                if u < 0 or not (math.isfinite(v1) and math.isfinite(soc1) and math.isfinite(dt)):
+                    status = -4                         # no admissible control from this state
+                    break
+                fuel += float(head[1, 6])
+                cost += float(head[1, 7])
+                s += 1
+                v, soc, t_abs = v1, soc1, t_abs + dt
+                if s < N_route:
+                    if v > float(r["vmax"][s]):
+                        violations += 1
+                    if v > 0.0 and _red_wait(r["lights"], s, t_abs) > 0.0:
+                        violations += 1                 # crossing a signal during red
+                if not (s_lo <= soc <= s_hi):
+                    status = -4
+                    break
+        finally:
+            gc.unfreeze()
         lat = [x["latency_ms"] for x in rows]
         return {
             "steps": rows, "stage": s, "v": v, "soc": soc, "t_abs": t_abs,
