@@ -295,6 +295,8 @@ template <> __device__ inline void time_lerp<17>(float (&T)[17], float rt)
 constexpr int kPrefetch = 4;
 // Rows of a next-stage plane one thread loads per pass when staging.
 constexpr int kStageRows = 8;
+// Most window rows of a prefetched next plane (held in registers).
+constexpr int kPrefRows = 17;
 // Value of the staged columns past the last time node (half the largest
 // float, so that sums of two of them stay finite).
 constexpr float kPad = 1.7014118e38f;
@@ -433,6 +435,16 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     int plane[2] = {-1, -1};
     int cur_p = -2;
     int SA = 0, SB = 0;   // LDS float offsets of the staged planes cur_p, cur_p + 1
+    // Controls come grouped by ascending successor speed cell, so after planes
+    // p, p+1 the next group usually needs p+1, p+2: plane p+2's window rows
+    // are loaded into registers while group p runs (windows of at most
+    // kPrefRows rows).  Only for tiles of at most 8 rows on time grids of at
+    // least 352 nodes: there the staged window of a workgroup of six or more
+    // waves already holds residency to about four waves per SIMD, so the
+    // registers cost no occupancy (on narrower grids they cost a wave).
+    constexpr bool kPref = JT <= 8 && PITCH >= 384;
+    float nxt[kPrefRows];
+    int nxt_p = -1;
 
     float pre[kPrefetch];
     auto fetch = [&](int c0) {
@@ -490,26 +502,42 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                         if (need_q) lds[sq * slot_sz + (rr + sh) * PITCH + t] = kPad;
                     }
                 }
+                // plane p+1 from the registers when it was prefetched
+                const bool from_pref = kPref && need_q && nxt_p == p + 1;
+                const bool load_q = need_q && !from_pref;
                 if (t < nt) {
+                    if (from_pref) {
+#pragma unroll
+                        for (int rr = 0; rr < kPrefRows; rr++)
+                            if (rr < nrows) lds[sq * slot_sz + (rr + sh) * PITCH + t] = nxt[rr];
+                    }
                     const float *srcp = Jn + (long)p * SV + (long)wlo * nt + t;
                     const float *srcq = srcp + SV;
-                    for (int r0 = 0; r0 < nrows; r0 += kStageRows) {
-                        float va[kStageRows], vb[kStageRows];
+                    if (need_p || load_q)
+                        for (int r0 = 0; r0 < nrows; r0 += kStageRows) {
+                            float va[kStageRows], vb[kStageRows];
 #pragma unroll
-                        for (int q = 0; q < kStageRows; q++) {
-                            const long off = (long)min(r0 + q, nrows - 1) * nt;
-                            va[q] = need_p ? srcp[off] : 0.0f;
-                            vb[q] = need_q ? srcq[off] : 0.0f;
-                        }
+                            for (int q = 0; q < kStageRows; q++) {
+                                const long off = (long)min(r0 + q, nrows - 1) * nt;
+                                va[q] = need_p ? srcp[off] : 0.0f;
+                                vb[q] = load_q ? srcq[off] : 0.0f;
+                            }
 #pragma unroll
-                        for (int q = 0; q < kStageRows; q++) {
-                            if (r0 + q < nrows) {
-                                if (need_p) lds[sp * slot_sz + (r0 + q + sh) * PITCH + t] = va[q];
-                                if (need_q) lds[sq * slot_sz + (r0 + q + sh) * PITCH + t] = vb[q];
+                            for (int q = 0; q < kStageRows; q++) {
+                                if (r0 + q < nrows) {
+                                    if (need_p) lds[sp * slot_sz + (r0 + q + sh) * PITCH + t] = va[q];
+                                    if (load_q) lds[sq * slot_sz + (r0 + q + sh) * PITCH + t] = vb[q];
+                                }
                             }
                         }
+                    // the likely next plane, in flight while this group runs
+                    if (kPref && nrows <= kPrefRows && p + 2 < P.n_v) {
+                        const float *srcn = srcq + SV;
+#pragma unroll
+                        for (int rr = 0; rr < kPrefRows; rr++) nxt[rr] = rr < nrows ? srcn[(long)rr * nt] : 0.0f;
                     }
                 }
+                nxt_p = (kPref && nrows <= kPrefRows && p + 2 < P.n_v) ? p + 2 : -1;
                 plane[sp] = p;
                 plane[sq] = p + 1;
                 SA = sp * slot_sz;
