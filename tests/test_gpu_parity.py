@@ -120,6 +120,24 @@ def test_plain_stage_isolated_every_stage(torch, kernel, tile):
     say("isolated mismatches (all in the near-tie band)", tot, "outside an absolute 1e-6 gap", tot_abs)
 
 
+@pytest.mark.parametrize("n_t", [78, 79, 94, 95, 15, 16])
+@pytest.mark.parametrize("tile,split", [(4, 1), (8, 3), (16, 1), (16, 2)])
+def test_partly_filled_last_wave(torch, n_t, tile, split):
+    # A sweep workgroup covers 63 time nodes per wave; its last wave holds
+    # r = n_t - 63 (waves - 1) of them.  n_t = 78/79 and 94/95 give two waves
+    # with r = 15/16 and 31/32 (a quarter or a half of the lanes, and one
+    # more), 15/16 one wave.  19 SoC rows leave a short last tile (irregular
+    # records for the 8- and 16-row tiles); every stage is compared with the
+    # oracle on every node, with and without control slices.
+    inst = ins.tiny(seed=501 + n_t, N=4, n_v=9, n_s=19, n_t=n_t, n_e=5, n_m=5, light=True,
+                    t_f=2.0 * n_t)
+    say("partly filled last wave", "n_t", n_t, "tile", tile, "split", split)
+    r = oracle.solve(inst)
+    plan = Plan([inst], kernel=2, sweep_tile=tile, split=split)
+    for k in range(inst["N"]):
+        check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), inst["name"])
+
+
 @pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("idx", range(5))
 def test_ragged_and_edge_instances(torch, idx, kernel):
