@@ -220,6 +220,21 @@ int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
 int dp_adjoint_grade(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
                      void *scratch, double *grad_dev, double *dgrade_dev, void *stream);
 
+/* dp_adjoint plus the sensitivity of V_0 to the timing of every signal
+ * (Eq. 8: offset O, red time R, cycle C; Eq. 5c: a vehicle stopped at a red
+ * signal waits tau = R - phase, with phase = t_abs - O - n C for n whole
+ * cycles).  dspat_dev: double [sum over instances of 3 n_lights], instance b
+ * at the offset of the 3 n_lights of the instances before it, signal L of
+ * the instance (in the order of its light arrays) at 3 L + (0, 1, 2) =
+ * dV_0/d(O, R, C) with the policy fixed.  Only the wait moves with the
+ * timing: a wait node adds rho (w_t + dJ_{k+1}/dt) times dtau, with
+ * dtau/dO = dtau/dR = 1 and dtau/dC = n; the red flags of the time nodes are
+ * constant between switching instants and add nothing.  The wait sums are
+ * kept per signal in the scratch buffer.  Not a number where x0 has no
+ * admissible control (as grad_dev); DP_EINVAL if dspat_dev is NULL. */
+int dp_adjoint_spat(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
+                    void *scratch, double *grad_dev, double *dspat_dev, void *stream);
+
 /* With DP_TIMING: total device milliseconds and launch count of the state
  * sweep kernel over every dp_solve / dp_stage since the previous call
  * (synchronises on the recorded events, then starts a new count). */

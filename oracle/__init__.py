@@ -72,7 +72,7 @@ def _load():
     lib.or_solve.argtypes = [ins, d, i16, d, d, i32]
     lib.or_rollout.argtypes = [ins, i16, C.c_int32, d, i32]
     lib.or_tangent.argtypes = [ins, d, i16, C.c_int32, d]
-    lib.or_adjoint.argtypes = [ins, d, i16, C.c_int32, d, d, d, d, d, d, d, d]
+    lib.or_adjoint.argtypes = [ins, d, i16, C.c_int32, d, d, d, d, d, d, d, d, d]
     lib.or_count_evals.argtypes = [ins]
     lib.or_count_evals.restype = C.c_int64
     lib.or_num_threads.restype = C.c_int
@@ -255,11 +255,13 @@ def adjoint(inst, J, pi, u0, want_rho=False):
     ep = C.c_double()
     rho = np.empty((I.N + 1) * I.S) if want_rho else None
     dg = np.empty(I.N)
+    nl = len(I.l_stage)
+    ds = np.empty(3 * max(1, nl))
     _load().or_adjoint(I.ref, _ptr(J, C.c_double), _ptr(pi, C.c_int16), int(u0), _ptr(g, C.c_double),
                        _ptr(rs, C.c_double), _ptr(ab, C.c_double), _ptr(ec, C.c_double), C.byref(et), C.byref(ep),
-                       _ptr(rho, C.c_double), _ptr(dg, C.c_double))
+                       _ptr(rho, C.c_double), _ptr(dg, C.c_double), _ptr(ds, C.c_double))
     out = {"grad": g, "rho_sum": rs, "absorbed": ab, "exp_cost": ec, "exp_time": et.value, "exp_socpen": ep.value,
-           "dgrade": dg}
+           "dgrade": dg, "dspat": ds[:3 * nl].reshape(nl, 3)}
     if want_rho:
         out["rho"] = rho.reshape((I.N + 1,) + I.shape)
     return out

@@ -752,7 +752,7 @@ static void scatter(const or_inst *I, double *rho_next, double rho, cf_t v, cf_t
 
 void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, int32_t u0,
                 double grad[5], double *rho_sum, double *absorbed, double *exp_cost, double *exp_time,
-                double *exp_socpen, double *rho_all, double *dgrade)
+                double *exp_socpen, double *rho_all, double *dgrade, double *dspat)
 {
     const long S = slab_size(I);
     const steps_t h = steps_of(I);
@@ -768,7 +768,9 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
     if (exp_cost) for (int k = 0; k <= I->N; k++) exp_cost[k] = 0.0;
     if (rho_all) memset(rho_all, 0, sizeof(double) * S * (I->N + 1));
     if (dgrade) for (int k = 0; k < I->N; k++) dgrade[k] = NAN;   /* like grad, when x0 has no control */
+    if (dspat) for (int q = 0; q < 3 * I->n_lights; q++) dspat[q] = NAN;
     if (u0 < 0) goto done;
+    if (dspat) for (int q = 0; q < 3 * I->n_lights; q++) dspat[q] = 0.0;
     {
         /* the root step from x0 puts unit mass on the bracketing nodes of stage 1 */
         int a, b;
@@ -817,6 +819,22 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
                         g[T_WT] += r * tau;
                         etime += r * tau;
                         if (exp_cost) exp_cost[k] += r * wt * tau;
+                        if (dspat) {
+                            /* signal timing (Eq. 5c, Eq. 8): the wait value
+                             * w_t tau + J_{k+1}(t_m + tau) moves with tau =
+                             * R - phase, and phase = t - O - n C (n whole
+                             * cycles), so dtau/dO = dtau/dR = 1 and dtau/dC =
+                             * n.  The red masks are constant between switching
+                             * instants: their derivative is zero. */
+                            double gJ[3];
+                            interp_grad(I, Jn, cf_of((double)i, nv), cf_of((double)j, ns), t, gJ);
+                            const double dval = wt + gJ[2] / h.ht;
+                            const double t_abs = I->t0_abs + grid_val(0.0, I->t_f, nt, m);
+                            const double ncyc = nearbyint((t_abs - I->l_off[L] - phase) / I->l_cycle[L]);
+                            dspat[3 * L + 0] += r * dval;
+                            dspat[3 * L + 1] += r * dval;
+                            dspat[3 * L + 2] += r * dval * ncyc;
+                        }
                         scatter(I, rn, r, cf_of((double)i, nv), cf_of((double)j, ns), t);
                     } else if (u >= 0) {
                         int a, b;

@@ -90,10 +90,13 @@ void or_tangent(const or_inst *I, const double *J_all, const int16_t *pi_all, in
  * rho_sum[N+1] (total occupancy per stage), absorbed[N+1] (mass on nodes at
  * the infeasibility cost, which stops there), exp_cost[N+1] (expected stage
  * cost per stage, expected J_N at N), exp_time (expected total time),
- * exp_socpen (expected terminal (xi - xi_ref)^2), rho_all [(N+1)*S]. */
+ * exp_socpen (expected terminal (xi - xi_ref)^2), rho_all [(N+1)*S];
+ * dgrade[N] (dV_0/dG_k per step); dspat[3 * n_lights] (dV_0 with respect
+ * to each signal's offset, red time and cycle, in the order of the
+ * instance's signals). */
 void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, int32_t u0,
                 double grad[5], double *rho_sum, double *absorbed, double *exp_cost, double *exp_time,
-                double *exp_socpen, double *rho_all, double *dgrade);
+                double *exp_socpen, double *rho_all, double *dgrade, double *dspat);
 
 /* Evaluation counter of a full sweep (dense counting, Sec. IV). */
 int64_t or_count_evals(const or_inst *I);

@@ -259,6 +259,21 @@ class Plan:
                 "dp_adjoint_grade")
         return grad.view(self.n, 5), list(dg.split(Ns))
 
+    def adjoint_spat(self):
+        """dV_0/dtheta (FP64 [n, 5]) and dV_0 with respect to the offset, red
+        time and cycle of every signal (FP64, one [n_lights_b, 3] tensor per
+        instance, signals in the order of the instance's ``lights``), the
+        stored policy held fixed."""
+        torch = self.torch
+        grad = torch.empty(5 * self.n, dtype=torch.float64, device=self.V0.device)
+        nl = [len(x.ls) for x in self._descs]
+        ds = torch.empty(max(1, 3 * sum(nl)), dtype=torch.float64, device=self.V0.device)
+        L.check(self.lib.dp_adjoint_spat(self._h, C.c_void_p(self.J.data_ptr()), C.c_void_p(self.pi.data_ptr()),
+                                         C.c_void_p(self.u0.data_ptr()), C.c_void_p(self.scratch.data_ptr()),
+                                         C.c_void_p(grad.data_ptr()), C.c_void_p(ds.data_ptr()), self._stream()),
+                "dp_adjoint_spat")
+        return grad.view(self.n, 5), [x.view(-1, 3) for x in ds[:3 * sum(nl)].split([3 * n for n in nl])]
+
     def sweep_time(self):
         ms, n = C.c_double(), C.c_int32()
         L.check(self.lib.dp_sweep_time(self._h, C.byref(ms), C.byref(n)), "dp_sweep_time")

@@ -325,6 +325,47 @@ __device__ inline void block_add5(double g[5], double *gpart, double *gcrr = nul
     }
 }
 
+// The workgroup's sums of a and b into slot[2 blockIdx.x + 0, 1].
+__device__ inline void block_store2(double a, double b, double *slot)
+{
+    __shared__ double red2[16][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    if (lane == 0) {
+        red2[w][0] = a;
+        red2[w][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double x = 0.0;
+        for (int ww = 0; ww < nw; ww++) x += red2[ww][threadIdx.x];
+        slot[(long)blockIdx.x * 2 + threadIdx.x] = x;
+    }
+}
+
+// dV/dO, dV/dR and dV/dC of every signal L from the kAdjBlocks slot pairs of
+// its stage: offset and red time move the wait alike, the cycle by n whole
+// cycles per node (the red masks are constant between switching instants).
+__global__ void __launch_bounds__(64) k_adj_spat(int n_lights, const double *__restrict__ gspat,
+                                                 const double *__restrict__ grad, double *__restrict__ dspat)
+{
+#pragma clang fp contract(off)
+    const bool none = grad[0] != grad[0];   // x0 had no admissible control: not a number, like grad
+    for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < n_lights; L += gridDim.x * blockDim.x) {
+        double o = 0.0, c = 0.0;
+        for (int b = 0; b < kAdjBlocks; b++) {
+            o += gspat[((long)L * kAdjBlocks + b) * 2];
+            c += gspat[((long)L * kAdjBlocks + b) * 2 + 1];
+        }
+        dspat[3 * L + 0] = none ? grad[0] : o;
+        dspat[3 * L + 1] = none ? grad[0] : o;
+        dspat[3 * L + 2] = none ? grad[0] : c;
+    }
+}
+
 // dV/dG_k for every step k: the grade of step k enters only the road load,
 // like C_rr, with dF_road/dG = M g cos^3 a (1 - C_rr G) against dF_road/dC_rr
 // = M g cos a, so dV/dG_k is cos a (cos a - C_rr sin a) times step k's share
@@ -371,12 +412,14 @@ constexpr int kAdjChunk = 512;
 __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
                                                    const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
                                                    const double *__restrict__ rho, double *__restrict__ rho_next,
-                                                   double *__restrict__ gacc, double *__restrict__ gcrr)
+                                                   double *__restrict__ gacc, double *__restrict__ gcrr,
+                                                   double *__restrict__ gspat)
 {
 #pragma clang fp contract(off)
     __shared__ int s_list[kAdjChunk];
     __shared__ int s_cnt;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double sO = 0.0, sC = 0.0;   // signal timing: sum of rho dval/dtau, and of rho n dval/dtau
     const long S = (long)P.n_v * P.n_s * P.n_t;
     const int lane = threadIdx.x & 63;
     for (long c0 = blockIdx.x * (long)kAdjChunk; c0 < S; c0 += (long)gridDim.x * kAdjChunk) {
@@ -405,6 +448,17 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
                 const TLEntry e = tl[m];
                 g[3] += r * e.tau;
                 const long base = ((long)i * P.n_s + j) * P.n_t;
+                if (gspat) {
+                    // the wait value w_t tau + J_{k+1}(t_m + tau) moves with
+                    // tau = R - phase, phase = t - O - n C: dtau/dO = dtau/dR
+                    // = 1, dtau/dC = n (Eq. 5c, 8); the time derivative of the
+                    // lerp counts only strictly inside a cell
+                    double gt = 0.0;
+                    if (e.wf > 0.0 && e.wf < 1.0) gt = (double)Jn[base + e.wc + 1] - (double)Jn[base + e.wc];
+                    const double dval = P.wt + gt / P.ht;
+                    sO += r * dval;
+                    sC += r * dval * (double)e.ncyc;
+                }
                 if (1.0 - e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc], r * (1.0 - e.wf));
                 if (e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc + 1], r * e.wf);
             } else if (u >= 0) {
@@ -425,6 +479,7 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
         __syncthreads();   // the list is read before the next chunk rewrites it
     }
     block_add5(g, gacc, gcrr);
+    if (gspat) block_store2(sO, sC, gspat);
 }
 
 // Stage N: dV/dw_soc gains rho_N (xi - xi_ref)^2 on nodes below J_inf.
@@ -485,11 +540,20 @@ int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, do
 }
 
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
-                         const double *rho, double *rho_next, double *gacc, double *gstage, hipStream_t s)
+                         const double *rho, double *rho_next, double *gacc, double *gstage, double *gspat_L,
+                         hipStream_t s)
 {
     // kAdjBlocks workgroups walk the chunks, each adding into its own slot
+    // (and, at a signal, storing its pair of gspat_L)
     hipLaunchKernelGGL(k_adj_stage, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc,
-                       gstage ? gstage + (long)k * kAdjBlocks : nullptr);
+                       gstage ? gstage + (long)k * kAdjBlocks : nullptr, tl ? gspat_L : nullptr);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_adjoint_spat(int n_lights, const double *gspat, const double *grad, double *dspat, hipStream_t s)
+{
+    if (n_lights <= 0) return 0;
+    hipLaunchKernelGGL(k_adj_spat, dim3((n_lights + 63) / 64), dim3(64), 0, s, n_lights, gspat, grad, dspat);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -43,6 +43,7 @@ struct Inst {
     int N = 0;
     size_t S = 0;              // slab elements
     std::vector<int> light_of_stage;
+    int n_lights = 0;
     size_t J_off = 0, pi_off = 0, traj_off = 0;
     size_t scr_st = 0, scr_bat = 0, scr_rho = 0, scr_nf = 0, scr_pw = 0;
     int sweep = 0;             // 1 = simple per-node kernel, 2 = grouped LDS kernel
@@ -112,6 +113,7 @@ struct dp_plan {
     size_t scr_q = 0;                // 8 queue counters per sweep launch, then 8 for dp_stage
     size_t scr_gpart = 0;            // adjoint partial gradient sums
     size_t scr_gstage = 0;           // adjoint per-stage C_rr shares (grade sensitivities)
+    size_t scr_gspat = 0;            // adjoint per-signal wait sums (signal-timing sensitivities)
     int n_q_slots = 0;
     // independent sweep launches of a round run on these streams side by side
     static constexpr int kSide = 3;
@@ -234,6 +236,7 @@ void build_tl(double C, double R, double O, double t0_abs, double t_f, int n_t, 
                 e.wcost = (float)(wt * tau);
                 e.wf32 = (float)f;
                 e.wg32 = (float)(1.0 - f);
+                e.ncyc = (int32_t)std::nearbyint((t0_abs + tm - O - ph) / C);
             }
         }
         out[m] = e;
@@ -465,6 +468,10 @@ static int plan_rounds(dp_plan *p, size_t scr)
     for (const Inst &I : p->inst) max_N = std::max(max_N, I.N);
     p->scr_gstage = scr;  // adjoint: per-(stage, workgroup) C_rr shares for the grade sensitivities
     scr += align_up(sizeof(double) * adjoint_grade_slots() * (size_t)max_N, 256);
+    int max_L = 1;
+    for (const Inst &I : p->inst) max_L = std::max(max_L, I.n_lights);
+    p->scr_gspat = scr;   // adjoint: per-(signal, workgroup) pairs for the signal-timing sensitivities
+    scr += align_up(sizeof(double) * 2 * adjoint_grade_slots() * (size_t)max_L, 256);
     p->bytes_scratch = scr;
 
     const size_t b_inst = align_up(sizeof(DevInst) * n_inst, 256);
@@ -557,6 +564,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         vmax[b].resize(N + 1);
         for (int k = 0; k <= N; k++) vmax[b][k] = d.v_max ? d.v_max[k] : d.v_hi;
         I.light_of_stage.assign(N + 1, -1);
+        I.n_lights = d.n_lights;
         for (int L = 0; L < d.n_lights; L++) {
             I.light_of_stage[d.light_stage[L]] = L;
             lc[b].push_back(d.light_cycle[L]);
@@ -1184,7 +1192,7 @@ int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_d
 }
 
 static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch,
-                        double *grad_dev, double *dgrade_dev, void *stream)
+                        double *grad_dev, double *dgrade_dev, double *dspat_dev, void *stream)
 {
     if (!p) return fail(DP_EINVAL, "plan is NULL");
     if (!(p->flags & DP_STORE_ALL_V)) return fail(DP_ESTATE, "adjoint needs a plan built with DP_STORE_ALL_V");
@@ -1193,10 +1201,11 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    size_t dgrade_off = 0;
+    size_t dgrade_off = 0, dspat_off = 0;
     for (size_t b = 0; b < p->inst.size(); b++) {
         const Inst &I = p->inst[b];
         double *gstage = dgrade_dev ? (double *)((char *)scratch + p->scr_gstage) : nullptr;
+        double *gspat = dspat_dev && I.n_lights > 0 ? (double *)((char *)scratch + p->scr_gspat) : nullptr;
         double *rho_a = (double *)((char *)scratch + I.scr_rho);
         double *rho_b = rho_a + I.S;
         double *g = grad_dev + 5 * b;
@@ -1205,7 +1214,8 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
         double *gpart = (double *)((char *)scratch + p->scr_gpart);
         if (launch_fill_f64(g, 5, 0.0, s) || launch_fill_f64(rho_a, (long)I.S, 0.0, s) ||
             launch_fill_f64(gpart, 5L * 1024, 0.0, s) ||
-            (gstage && launch_fill_f64(gstage, (long)adjoint_grade_slots(), 0.0, s)))
+            (gstage && launch_fill_f64(gstage, (long)adjoint_grade_slots(), 0.0, s)) ||
+            (gspat && launch_fill_f64(gspat, 2L * (long)adjoint_grade_slots() * I.n_lights, 0.0, s)))
             return hip_fail(hipGetLastError(), "fill launch");
         if (launch_adjoint_root(I.P, Jb + I.S, u0_dev + b, rho_a, g, gstage, s))
             return hip_fail(hipGetLastError(), "adjoint root launch");
@@ -1213,8 +1223,9 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
             const int L = I.light_of_stage[k];
             const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
             if (launch_fill_f64(rho_b, (long)I.S, 0.0, s)) return hip_fail(hipGetLastError(), "fill launch");
+            double *gspat_L = gspat && L >= 0 ? gspat + 2 * adjoint_grade_slots() * (size_t)L : nullptr;
             if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, rho_a, rho_b, gpart,
-                                     gstage, s))
+                                     gstage, gspat_L, s))
                 return hip_fail(hipGetLastError(), "adjoint stage launch");
             double *t = rho_a;
             rho_a = rho_b;
@@ -1225,7 +1236,10 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
         if (launch_adjoint_reduce(gpart, g, s)) return hip_fail(hipGetLastError(), "adjoint reduce launch");
         if (gstage && launch_adjoint_grade(I.P, gstage, g, dgrade_dev + dgrade_off, s))
             return hip_fail(hipGetLastError(), "adjoint grade launch");
+        if (gspat && launch_adjoint_spat(I.n_lights, gspat, g, dspat_dev + dspat_off, s))
+            return hip_fail(hipGetLastError(), "adjoint signal-timing launch");
         dgrade_off += (size_t)I.N;
+        dspat_off += 3 * (size_t)I.n_lights;
     }
     return DP_OK;
 }
@@ -1233,14 +1247,21 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
 int dp_adjoint(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch, double *grad_dev,
                void *stream)
 {
-    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, nullptr, stream);
+    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, nullptr, nullptr, stream);
 }
 
 int dp_adjoint_grade(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch,
                      double *grad_dev, double *dgrade_dev, void *stream)
 {
     if (!dgrade_dev) return fail(DP_EINVAL, "NULL grade-sensitivity buffer");
-    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, dgrade_dev, stream);
+    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, dgrade_dev, nullptr, stream);
+}
+
+int dp_adjoint_spat(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev, void *scratch,
+                    double *grad_dev, double *dspat_dev, void *stream)
+{
+    if (!dspat_dev) return fail(DP_EINVAL, "NULL signal-timing sensitivity buffer");
+    return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, nullptr, dspat_dev, stream);
 }
 
 int dp_sweep_time(dp_plan *p, double *ms, int32_t *launches)

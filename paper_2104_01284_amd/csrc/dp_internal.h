@@ -40,7 +40,11 @@ int launch_fill_f64(double *p, long n, double v, hipStream_t s);
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
                         double *gstage, hipStream_t s);
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
-                         const double *rho, double *rho_next, double *gacc, double *gstage, hipStream_t s);
+                         const double *rho, double *rho_next, double *gacc, double *gstage, double *gspat_L,
+                         hipStream_t s);
+// dspat[3 L + (0, 1, 2)] = dV/d(offset, red, cycle) of signal L from the
+// adjoint_grade_slots() slot pairs per signal in gspat.
+int launch_adjoint_spat(int n_lights, const double *gspat, const double *grad, double *dspat, hipStream_t s);
 int launch_adjoint_grade(const DevInst &P, const double *gstage, const double *grad, double *dgrade, hipStream_t s);
 size_t adjoint_grade_slots();
 // gpart: the adjoint kernels' per-workgroup partial gradient sums (1024 x 5

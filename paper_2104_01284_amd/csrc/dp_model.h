@@ -75,7 +75,7 @@ struct TLEntry {
     double tau;    // wait: time to the end of red [s]
     float wcost;   // w_t * tau rounded to FP32
     float wf32, wg32;
-    float pad;
+    int32_t ncyc;  // whole cycles n in t_abs - O = n C + phase (dtau/dC = n)
 };
 
 // One (instance, stage) of the grouped sweep.  Buffer positions are byte

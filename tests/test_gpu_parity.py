@@ -381,3 +381,45 @@ def test_grade_sensitivities_match_oracle(torch):
         ao = oracle.adjoint(inst, J32, r["pi"], r["u0"])
         np.testing.assert_allclose(dg[0].cpu().numpy(), ao["dgrade"], rtol=1e-9, atol=1e-12)
         np.testing.assert_allclose(g5.cpu().numpy()[0], ao["grad"], rtol=1e-9, atol=1e-12)
+
+
+def test_signal_timing_sensitivities_match_oracle(torch):
+    """dV_0 with respect to each signal's offset, red time and cycle
+    (dp_adjoint_spat) on the oracle's own solve loaded into the plan, against
+    the oracle's adjoint on the same FP32-rounded values (1e-9): a route whose
+    first signal holds the vehicle one whole cycle after its offset, the same
+    route in a two-instance plan behind one without signals, and the
+    16-step route with three signals whose waits fall 0, 2 and 4 whole cycles
+    after their offsets."""
+    t = ins.tiny(seed=600, N=8, n_v=11, n_s=7, n_t=41, n_e=5, n_m=5, light=True, t_f=60.0)
+    t["v0"] = 1.0
+    t["lights"] = [(1, 40.0, 25.0, t["t0_abs"] - 42.0), (5, 30.0, 12.0, t["t0_abs"] + 7.0)]
+    flat = ins.tiny(seed=602, N=5, n_v=7, n_s=5, n_t=21, n_e=3, n_m=3, light=False, t_f=40.0)
+    w = ins.tiny(seed=603, N=16, n_v=13, n_s=9, n_t=61, n_e=5, n_m=5, light=True, t_f=120.0)
+    w["v0"] = 1.5
+    t0 = w["t0_abs"]
+    w["lights"] = [(1, 35.0, 20.0, t0 - 3.0), (7, 30.0, 14.0, t0 - 35.0), (12, 25.0, 15.0, t0 - 40.0)]
+    for group in ([t], [flat, t], [w]):
+        say("signal-timing sensitivities", [x["name"] for x in group])
+        sols = [oracle.solve(x) for x in group]
+        plan = Plan(group, store_all=True)
+        plan.solve()
+        for b, (x, r) in enumerate(zip(group, sols)):
+            plan.values(b).copy_(torch.from_numpy(r["J"].astype(np.float32)).cuda())
+            plan.policy(b).copy_(torch.from_numpy(r["pi"]).cuda())
+            plan.u0[b] = int(r["u0"])
+        torch.cuda.synchronize()
+        g5, ds = plan.adjoint_spat()
+        g_only = plan.adjoint()
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(g5.cpu().numpy(), g_only.cpu().numpy(), rtol=1e-12, atol=1e-15)
+        assert len(ds) == len(group)
+        for b, (x, r) in enumerate(zip(group, sols)):
+            J32 = r["J"].astype(np.float32).astype(np.float64)
+            ao = oracle.adjoint(x, J32, r["pi"], r["u0"])
+            got = ds[b].cpu().numpy()
+            assert got.shape == (len(x["lights"]), 3)
+            np.testing.assert_allclose(got, ao["dspat"], rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(g5.cpu().numpy()[b], ao["grad"], rtol=1e-9, atol=1e-12)
+        if group[-1] is t:
+            assert ds[-1][0, 0].item() != 0.0

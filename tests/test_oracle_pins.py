@@ -629,3 +629,63 @@ def test_grade_sensitivities_fd():
         assert checked >= 3, base["name"]
         if np.all(np.asarray(base["grade"]) == 0.0):
             assert dg.sum() == pytest.approx(ad["grad"][2], rel=1e-12)
+
+
+def _spat_instance(seed):
+    """A vehicle that starts slowly towards a signal one step ahead that is
+    red for the first 23 s of the horizon, one whole cycle after its offset
+    (so the waits there have n = 1), and a second signal further on."""
+    inst = ins.tiny(seed=seed, N=8, n_v=11, n_s=7, n_t=41, n_e=5, n_m=5, light=True, t_f=60.0)
+    inst["v0"] = 1.0
+    t0 = inst["t0_abs"]
+    inst["lights"] = [(1, 40.0, 25.0, t0 - 42.0), (5, 30.0, 12.0, t0 + 7.0)]
+    return inst
+
+
+def _spat_moved(inst, L, q, d):
+    x = copy.deepcopy(inst)
+    lights = [list(t) for t in x["lights"]]
+    lights[L][q] += d
+    x["lights"] = [tuple(t) for t in lights]
+    return x
+
+
+def test_signal_timing_sensitivities_fd():
+    """dV_0 with respect to each signal's offset, red time and cycle (Eq. 5c,
+    Eq. 8) from the occupancy sweep: central differences of fresh solves agree
+    where the policy stays the same; offset and red time move the wait alike,
+    and for waits one whole cycle after the offset the cycle does too."""
+    checked = 0
+    for seed in (600, 605, 613):
+        inst = _spat_instance(seed)
+        r = oracle.solve(inst)
+        ad = oracle.adjoint(inst, r["J"], r["pi"], r["u0"], want_rho=True)
+        ds = ad["dspat"]
+        assert ds.shape == (2, 3)
+        # the first signal holds the vehicle: occupied wait nodes, so the pin
+        # is not vacuous
+        assert ((r["pi"][1] == -2) & (ad["rho"][1] > 0)).any()
+        assert ds[0, 0] != 0.0
+        assert ds[0, 0] == ds[0, 1] and ds[1, 0] == ds[1, 1]
+        assert ds[0, 2] == pytest.approx(ds[0, 0], rel=1e-12)
+        for L in range(2):
+            for q, col in ((3, 0), (2, 1), (1, 2)):
+                for h in (1e-5, 1e-6):
+                    sols = [oracle.solve(_spat_moved(inst, L, q, d)) for d in (h, -h)]
+                    if all(s_["u0"] == r["u0"] and np.array_equal(s_["pi"], r["pi"]) for s_ in sols):
+                        fd = (sols[0]["V0"] - sols[1]["V0"]) / (2 * h)
+                        assert fd == pytest.approx(ds[L, col], rel=1e-5, abs=1e-8), (seed, L, q, h, fd, ds[L])
+                        checked += 1
+                        break
+    assert checked >= 15
+
+
+def test_signal_timing_sensitivities_without_waits():
+    """With waiting at red switched off no node waits, and the timing enters
+    only through the red flags, which are constant between switching
+    instants: every signal-timing derivative is zero."""
+    inst = ins.tiny(seed=401, N=12, n_v=11, n_s=7, n_t=41, n_e=5, n_m=5, light=True, t_f=60.0, wait=False)
+    r = oracle.solve(inst)
+    assert r["u0"] >= 0 and len(inst["lights"]) == 1
+    ad = oracle.adjoint(inst, r["J"], r["pi"], r["u0"])
+    assert ad["dspat"].shape == (1, 3) and np.all(ad["dspat"] == 0.0)
