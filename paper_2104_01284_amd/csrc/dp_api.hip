@@ -348,7 +348,7 @@ static int plan_rounds(dp_plan *p, size_t scr)
             ns = std::max(1, std::min(ns, std::min(16, I.P.n_u)));
             I.nsplit = std::max(I.nsplit, ns);
             const int pitch = sweep_pitch(I.P.n_t);
-            const int threads = sweep_threads(I.P.n_t);
+            const int threads = sweep_threads(I.jt, I.P.n_t);
             t.push_back({b, I.jt, pitch, threads, ns, (double)I.P.n_u / ns});
         }
         std::stable_sort(t.begin(), t.end(), [](const Tmp &x, const Tmp &y) {
@@ -704,20 +704,22 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         // state-sweep variant: the grouped LDS kernel when its tables and
         // staged planes fit, else the simple per-node kernel
         I.H = soc_shift_bound(P, d);
-        // SoC rows per workgroup: the largest tile that still leaves five
-        // resident waves per SIMD (the sweep waits on LDS and barriers, so
-        // resident waves matter more than the per-tile saving), six in a
-        // batch, where the launches of a round share the CUs; else the tile
-        // with the most; a caller tile overrides
+        // SoC rows per workgroup: 8-row tiles when they leave five resident
+        // waves per SIMD (the sweep waits on LDS and barriers, so resident
+        // waves matter more than the per-tile saving), six in a batch, where
+        // the launches of a round share the CUs; else 16 rows on two wave
+        // groups, then 4, by the same bound; else the tile with the most
+        // resident waves; a caller tile (or the autotuner) overrides
         const double min_waves = n_inst > 1 ? 6.0 : 5.0;
         const size_t lds_cu = (size_t)p->lds_per_cu;
-        const int waves = (d.n_t + 62) / 63;
         // resident waves per SIMD of the grouped sweep with tile t: bounded by
         // the LDS of a CU, by 8 waves per SIMD and by the kernel's registers
-        // (512 per SIMD lane, allocated in granules of 8)
+        // (512 per SIMD lane, allocated in granules of 8); 0 when its
+        // workgroup would exceed 1024 threads
         auto waves_per_simd = [&](int t) {
             const size_t bytes = lds_sweep_bytes(t, I.H, d.n_t);
-            if (bytes > lds_cu) return 0.0;
+            const int waves = sweep_threads(t, d.n_t) / 64;
+            if (bytes > lds_cu || waves > 16) return 0.0;
             size_t wg = lds_cu / bytes;
             if (wg * waves > 32) wg = 32 / waves;
             const int vg = (sweep_vgprs(t, sweep_pitch(d.n_t)) + 7) / 8 * 8;
@@ -732,8 +734,9 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         I.wg_opt = io && io[3] ? io[3] : p->opt.tile[2];
         if (o_tile == 4 || o_tile == 8 || o_tile == 16) {
             jt = o_tile;
+            if (sweep_threads(jt, d.n_t) > 1024) jt = 8;   // 16-row tiles need n_t <= 504
         } else {
-            const int cand[3] = {16, 8, 4};
+            const int cand[3] = {8, 16, 4};
             double best_w = 0.0;
             for (int t : cand) {
                 if (t > 4 && d.n_soc < t) continue;
@@ -750,7 +753,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             if (jt == 0) jt = 4;
         }
         const bool lds_fits = lds_sweep_bytes(jt, I.H, d.n_t) + lds_job_index_bytes(n_inst) <= lds_cu &&
-                              d.n_t <= 1008 && P.n_u <= 1024 && d.n_v - 1 <= kSortBins &&
+                              sweep_threads(jt, d.n_t) <= 1024 && P.n_u <= 1024 && d.n_v - 1 <= kSortBins &&
                               I.H <= 120;   // cell offsets in the records are bytes
         I.jt = jt;
         I.sweep = o_kernel == 1 ? 1 : (lds_fits ? 2 : 1);
@@ -762,6 +765,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         }
         if (lds_fits) {
             size_t wg = lds_cu / lds_sweep_bytes(jt, I.H, d.n_t);
+            const int waves = sweep_threads(jt, d.n_t) / 64;
             if (wg * waves > 32) wg = 32 / waves;
             if (I.wg_opt > 0 && (size_t)I.wg_opt < wg) wg = I.wg_opt;
             if (wg < 1) wg = 1;
@@ -1100,7 +1104,7 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
         return hip_fail(hipGetLastError(), "stage table launch");
     int rc = time_begin(p, s);
     if (rc) return rc;
-    const int pitch = sweep_pitch(I.P.n_t), threads = sweep_threads(I.P.n_t);
+    const int pitch = sweep_pitch(I.P.n_t), threads = sweep_threads(I.jt, I.P.n_t);
     if (launch_sweep_jobs(I.jt, pitch, threads, B, 1, nullptr, j.nitems, q, I.grid,
                           lds_sweep_bytes(I.jt, I.H, I.P.n_t), s))
         return hip_fail(hipGetLastError(), "sweep launch");

@@ -19,10 +19,11 @@ int launch_root(const DevInst *Pdev, const float *J1, float *V0, int16_t *u0, hi
 // least one padding column, rounded up to 32 so that the rows of a small grid
 // do not waste LDS), staged SoC rows
 // of a tile of JT rows whose successor cells move by at most H, and threads
-// per workgroup (a wave covers 63 time nodes plus the neighbour of the last).
+// per workgroup (a wave covers 63 time nodes plus the neighbour of the last;
+// a tile of more than 8 rows runs on JT / 8 such groups of waves).
 inline int sweep_pitch(int n_t) { return ((n_t + 1 + 31) / 32) * 32; }
 inline int sweep_rows(int JT, int H) { return JT + 2 * H + 1; }
-inline int sweep_threads(int n_t) { return 64 * ((n_t + 62) / 63); }
+inline int sweep_threads(int JT, int n_t) { return (JT > 8 ? JT / 8 : 1) * 64 * ((n_t + 62) / 63); }
 
 // Grouped sweep over a table of (instance, stage) jobs.
 int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_records, hipStream_t s);

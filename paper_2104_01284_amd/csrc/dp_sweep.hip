@@ -407,14 +407,25 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     const int nrows = whi - wlo + 1;
     const int wbase = j0 - H;
     const int sh = wlo - wbase;
+    // A tile of more than 8 rows runs on JT / 8 groups of waves, group g
+    // taking rows 8 g ... 8 g + 7 of the tile: the groups share one staged
+    // window (2H + 1 rows fewer per tile row than separate workgroups) and
+    // each wave keeps the registers of an 8-row tile.  A wave covers 63
+    // consecutive time nodes of its group's rows (its last lane is the halo
+    // of the time lerp).
+    constexpr int R = JT > 8 ? 8 : JT;          // tile rows per wave
+    constexpr int NG = JT / R;                  // wave groups per workgroup
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = wave * 63 + lane;
+    const int gthreads = (int)blockDim.x / NG;  // threads per group
+    const int grp = __builtin_amdgcn_readfirstlane(NG > 1 ? (int)threadIdx.x / gthreads : 0);
+    const int qb = grp * R;                     // first tile row of this wave
+    const int m = (wave - grp * (gthreads >> 6)) * 63 + lane;
     const bool out_lane = lane < 63 && m < nt;
     const float Jinf = P.Jinf;
-    float best[JT];
-    int bu[JT];
+    float best[R];
+    int bu[R];
 #pragma unroll
-    for (int q = 0; q < JT; q++) {
+    for (int q = 0; q < R; q++) {
         best[q] = Jinf;
         bu[q] = -1;
     }
@@ -485,11 +496,17 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                     sq = 1 - sp;
                 }
                 __syncthreads();
-                // thread t copies time node t (the block has at least n_t
-                // threads) of kStageRows rows per pass, all loads in flight
-                // before the LDS stores
-                const int t = threadIdx.x;
-                if (t >= nt && t < PITCH) {
+                // thread t of a group copies time node t (a group has at
+                // least n_t threads) of kStageRows rows per pass, all loads in
+                // flight before the LDS stores; group g takes passes g, g +
+                // NG, ...
+                int t = threadIdx.x;
+                if (NG > 1) {
+                    // the thread's index within its group, formed here (not
+                    // kept in a register across the control loop)
+                    asm volatile("v_subrev_u32 %0, %1, %0" : "+v"(t) : "s"(grp * gthreads));
+                }
+                if (grp == 0 && t >= nt && t < PITCH) {
                     // columns past the last time node hold a huge finite value:
                     // a candidate whose successor time leaves the grid (or sits
                     // on the last node with a positive fraction) is then far
@@ -514,7 +531,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                     const float *srcp = Jn + (long)p * SV + (long)wlo * nt + t;
                     const float *srcq = srcp + SV;
                     if (need_p || load_q)
-                        for (int r0 = 0; r0 < nrows; r0 += kStageRows) {
+                        for (int r0 = grp * kStageRows; r0 < nrows; r0 += NG * kStageRows) {
                             float va[kStageRows], vb[kStageRows];
 #pragma unroll
                             for (int q = 0; q < kStageRows; q++) {
@@ -550,22 +567,23 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             const int u = __float_as_int(ce[7]);
             const int pos = m + dtc;
             const float *wp = ce + rec_weights(JT);
-            float Qv[JT];
+            float Qv[R];
             if (hdr >= 0) {
                 // successor times past the grid read the padding columns
                 const int posc = min(pos, PITCH - 1);
                 const float c = c0f;
-                const int a0 = SA + hdr * PITCH + posc;
-                const int b0 = SB + hdr * PITCH + posc;
-                // speed lerp on the JT+1 SoC rows, then the time lerp with
+                const int a0 = SA + (hdr + qb) * PITCH + posc;
+                const int b0 = SB + (hdr + qb) * PITCH + posc;
+                const float *w = wp + 2 * qb;
+                // speed lerp on the R+1 SoC rows, then the time lerp with
                 // the neighbouring lane (scaled by 1/gt), then the SoC lerp
                 // per node (weights scaled by gt)
-                float T[JT + 1];
+                float T[R + 1];
 #pragma unroll
-                for (int q = 0; q <= JT; q++) T[q] = fmaf(fv, lds[b0 + q * PITCH], gv * lds[a0 + q * PITCH]);
+                for (int q = 0; q <= R; q++) T[q] = fmaf(fv, lds[b0 + q * PITCH], gv * lds[a0 + q * PITCH]);
                 time_lerp(T, rt);
 #pragma unroll
-                for (int q = 0; q < JT; q++) Qv[q] = fmaf(wp[2 * q], T[q + 1], fmaf(wp[2 * q + 1], T[q], c));
+                for (int q = 0; q < R; q++) Qv[q] = fmaf(w[2 * q], T[q + 1], fmaf(w[2 * q + 1], T[q], c));
             } else {
                 const bool okt = out_lane && (pos < nt - 1 || (pos == nt - 1 && ft == 0.0f));
                 const int posc = min(pos, nt - 1);
@@ -573,13 +591,14 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                 // stage cost, so their candidates never win
                 const float c = okt ? c0f : __builtin_inff();
                 // the rows' cells, four int8 offsets per dword (wave-uniform)
-                int cw[JT / 4];
+                int cw[R / 4];
 #pragma unroll
-                for (int w = 0; w < JT / 4; w++) cw[w] = __builtin_amdgcn_readfirstlane(__float_as_int(ce[rec_cells(JT) + w]));
+                for (int w = 0; w < R / 4; w++)
+                    cw[w] = __builtin_amdgcn_readfirstlane(__float_as_int(ce[rec_cells(JT) + qb / 4 + w]));
 #pragma unroll
-                for (int q = 0; q < JT; q++) {
+                for (int q = 0; q < R; q++) {
                     const int off = (int)(int8_t)(cw[q / 4] >> (8 * (q % 4)));
-                    const int jx = q < jc && off != kNoCell ? j0 + q + off : -1;
+                    const int jx = qb + q < jc && off != kNoCell ? j0 + qb + q + off : -1;
                     Qv[q] = Jinf;
                     if (jx >= 0) {
                         float T2[2];
@@ -594,12 +613,12 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                             T2[1] = fmaf(fv, a[SV + nt], gv * a[nt]);
                         }
                         time_lerp(T2, rt);
-                        Qv[q] = fmaf(wp[2 * q], T2[1], fmaf(wp[2 * q + 1], T2[0], c));
+                        Qv[q] = fmaf(wp[2 * (qb + q)], T2[1], fmaf(wp[2 * (qb + q) + 1], T2[0], c));
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < JT; q++) {
+            for (int q = 0; q < R; q++) {
                 const bool upd = Qv[q] < best[q];
                 best[q] = upd ? Qv[q] : best[q];
                 bu[q] = upd ? u : bu[q];
@@ -610,9 +629,9 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
         // partial minimum of this control slice; the combine kernel finishes
         const long plane_nodes = (long)P.n_v * SV;
 #pragma unroll
-        for (int q = 0; q < JT; q++) {
-            if (q < jc) {
-                const long n = ((long)i * ns + j0 + q) * nt + m;
+        for (int q = 0; q < R; q++) {
+            if (qb + q < jc) {
+                const long n = ((long)i * ns + j0 + qb + q) * nt + m;
                 part_v[split * plane_nodes + n] = best[q];
                 part_u[split * plane_nodes + n] = (int16_t)bu[q];
             }
@@ -622,9 +641,9 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
         const bool has_tl = tl != nullptr;
         if (has_tl) t = tl[m];
 #pragma unroll
-        for (int q = 0; q < JT; q++) {
-            if (q < jc) {
-                const int j = j0 + q;
+        for (int q = 0; q < R; q++) {
+            if (qb + q < jc) {
+                const int j = j0 + qb + q;
                 float J = best[q];
                 int pu = bu[q];
                 if (has_tl && t.red) {
@@ -714,7 +733,7 @@ int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_record
 size_t lds_sweep_bytes(int JT, int H, int n_t)
 {
     return sizeof(float) * (2 * (size_t)sweep_rows(JT, H) * sweep_pitch(n_t) +
-                            (size_t)kPrefetch * sweep_threads(n_t));
+                            (size_t)kPrefetch * sweep_threads(JT, n_t));
 }
 
 size_t lds_job_index_bytes(int njobs) { return njobs > 1 ? sizeof(int) * (size_t)(((njobs + 64) / 64) * 64) : 0; }
