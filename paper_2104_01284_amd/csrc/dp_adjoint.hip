@@ -409,6 +409,9 @@ __global__ void __launch_bounds__(256) k_adj_reduce(const double *__restrict__ g
 // grid) and then runs the FP64 work on full waves.
 constexpr int kAdjChunk = 512;
 
+// SPAT: also the signal-timing sums of the wait nodes (a separate instance, so
+// that the plain adjoint keeps its registers).
+template <bool SPAT>
 __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
                                                    const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
                                                    const double *__restrict__ rho, double *__restrict__ rho_next,
@@ -448,7 +451,7 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
                 const TLEntry e = tl[m];
                 g[3] += r * e.tau;
                 const long base = ((long)i * P.n_s + j) * P.n_t;
-                if (gspat) {
+                if (SPAT) {
                     // the wait value w_t tau + J_{k+1}(t_m + tau) moves with
                     // tau = R - phase, phase = t - O - n C: dtau/dO = dtau/dR
                     // = 1, dtau/dC = n (Eq. 5c, 8); the time derivative of the
@@ -479,7 +482,7 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
         __syncthreads();   // the list is read before the next chunk rewrites it
     }
     block_add5(g, gacc, gcrr);
-    if (gspat) block_store2(sO, sC, gspat);
+    if (SPAT) block_store2(sO, sC, gspat);
 }
 
 // Stage N: dV/dw_soc gains rho_N (xi - xi_ref)^2 on nodes below J_inf.
@@ -545,8 +548,13 @@ int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t
 {
     // kAdjBlocks workgroups walk the chunks, each adding into its own slot
     // (and, at a signal, storing its pair of gspat_L)
-    hipLaunchKernelGGL(k_adj_stage, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next, gacc,
-                       gstage ? gstage + (long)k * kAdjBlocks : nullptr, tl ? gspat_L : nullptr);
+    double *gcrr = gstage ? gstage + (long)k * kAdjBlocks : nullptr;
+    if (tl && gspat_L)
+        hipLaunchKernelGGL(k_adj_stage<true>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next,
+                           gacc, gcrr, gspat_L);
+    else
+        hipLaunchKernelGGL(k_adj_stage<false>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next,
+                           gacc, gcrr, nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -708,8 +708,9 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         // waves per SIMD (the sweep waits on LDS and barriers, so resident
         // waves matter more than the per-tile saving), six in a batch, where
         // the launches of a round share the CUs; else 16 rows on two wave
-        // groups, then 4, by the same bound; else the tile with the most
-        // resident waves; a caller tile (or the autotuner) overrides
+        // groups (single instances only), then 4, by the same bound; else
+        // the tile with the most resident waves; a caller tile (or the
+        // autotuner) overrides
         const double min_waves = n_inst > 1 ? 6.0 : 5.0;
         const size_t lds_cu = (size_t)p->lds_per_cu;
         // resident waves per SIMD of the grouped sweep with tile t: bounded by
@@ -740,6 +741,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             double best_w = 0.0;
             for (int t : cand) {
                 if (t > 4 && d.n_soc < t) continue;
+                if (t == 16 && n_inst > 1) continue;   // measured slower in a batch
                 const double w = waves_per_simd(t);
                 if (w >= min_waves) {
                     jt = t;
