@@ -568,7 +568,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             const int pos = m + dtc;
             const float *wp = ce + rec_weights(JT);
             float Qv[R];
-            if (hdr >= 0) {
+            // a wave group of a 16-row tile with at most half of its rows
+            // inside the tile (the last tile of the grid) takes the general
+            // path, which runs only those rows
+            if (hdr >= 0 && (NG == 1 || 2 * (jc - qb) > R)) {
                 // successor times past the grid read the padding columns
                 const int posc = min(pos, PITCH - 1);
                 const float c = c0f;

@@ -138,6 +138,21 @@ def test_partly_filled_last_wave(torch, n_t, tile, split):
         check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), inst["name"])
 
 
+@pytest.mark.parametrize("n_s", [25, 28, 29, 40])
+@pytest.mark.parametrize("split", [1, 2])
+def test_sixteen_row_tiles_short_last_tile(torch, n_s, split):
+    # 16-row tiles run on two wave groups of 8 rows; the last tile holds 9,
+    # 12, 13 or 8 rows, so its second group has 1, 4, 5 or no rows inside
+    # the tile (at most half: general path; more: regular path).  Every
+    # stage on every node against the oracle.
+    inst = ins.tiny(seed=700 + n_s, N=4, n_v=9, n_s=n_s, n_t=70, n_e=5, n_m=5, light=True, t_f=100.0)
+    say("16-row tiles", "n_s", n_s, "split", split)
+    r = oracle.solve(inst)
+    plan = Plan([inst], kernel=2, sweep_tile=16, split=split)
+    for k in range(inst["N"]):
+        check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), inst["name"])
+
+
 @pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("idx", range(5))
 def test_ragged_and_edge_instances(torch, idx, kernel):
@@ -251,15 +266,16 @@ def test_multi_instance_plan_equals_single(torch):
         assert torch.equal(big.policy(b), one.policy(0))
 
 
-def test_realistic_against_golden(torch):
+@pytest.mark.parametrize("tile", [0, 16])
+def test_realistic_against_golden(torch, tile):
     path = os.path.join(GOLDEN, "realistic_oracle.json")
     if not os.path.exists(path):
         pytest.skip("golden file not generated")
     with open(path) as f:
         g = json.load(f)
     inst = ins.realistic()
-    say("realistic_2km full solve")
-    plan = Plan([inst], store_all=True)
+    say("realistic_2km full solve, tile", tile)
+    plan = Plan([inst], store_all=True, sweep_tile=tile)
     V0, u0 = plan.solve()
     torch.cuda.synchronize()
     Vg = float(V0.cpu()[0])
@@ -275,11 +291,13 @@ def test_realistic_against_golden(torch):
     assert err.max() < 1e-4
 
 
-def test_realistic_sampled_isolated_stages(torch):
-    """Full-size launch configuration: a seeded J_{k+1} fed to both the GPU
-    step and the oracle, compared on sampled nodes."""
+@pytest.mark.parametrize("tile", [0, 16])
+def test_realistic_sampled_isolated_stages(torch, tile):
+    """Full-size launch configuration (the automatic tile, and the 16-row
+    tile the benchmark's autotuner picks): a seeded J_{k+1} fed to both the
+    GPU step and the oracle, compared on sampled nodes."""
     inst = ins.realistic()
-    plan = Plan([inst], store_all=True)
+    plan = Plan([inst], store_all=True, sweep_tile=tile)
     plan.solve()
     torch.cuda.synchronize()
     rng = np.random.default_rng(9)
