@@ -323,8 +323,10 @@ static int plan_rounds(dp_plan *p, size_t scr)
     // about 20 items per CU, so that the last items of a launch are short
     // against the whole; a slice costs a partial-result store and a share
     // of the combine (measured best: 8-10 slices on realistic_2km, 4 on
-    // large_3km)
-    const long target = 20L * p->n_cu;
+    // large_3km).  Items of 16-row tiles carry twice the rows and three of
+    // their workgroups fit per CU instead of five: about 12 per CU keeps
+    // some four items per resident workgroup (measured best 10-12 slices
+    // on realistic_2km with 16-row tiles).
     for (int r = 0; r < maxN; r++) {
         Round &R = p->rounds[r];
         long base = 0;
@@ -339,6 +341,9 @@ static int plan_rounds(dp_plan *p, size_t scr)
                 R.simple.push_back(b);
             }
         }
+        bool wide = !members.empty();
+        for (int b : members) wide = wide && p->inst[b].jt > 8;
+        const long target = (wide ? 12L : 20L) * p->n_cu;
         const int ns_round = (int)std::min<long>(16, std::max<long>(1, (target + base - 1) / std::max(1L, base)));
         struct Tmp { int b, cls_jt, cls_pitch, cls_threads, ns; double cost; };
         std::vector<Tmp> t;
