@@ -441,3 +441,27 @@ def test_signal_timing_sensitivities_match_oracle(torch):
             np.testing.assert_allclose(g5.cpu().numpy()[b], ao["grad"], rtol=1e-9, atol=1e-12)
         if group[-1] is t:
             assert ds[-1][0, 0].item() != 0.0
+
+
+def test_signal_timing_sensitivities_edge_cases(torch):
+    """No admissible control from x0 (every first step outlasts a 1 s time
+    grid): the oracle and dp_adjoint_spat both give not-a-number for every
+    signal, like the theta gradient; a plan without the stored value slabs is
+    refused (DP_ESTATE)."""
+    from paper_2104_01284_amd._lib import DPError
+    t = ins.tiny(seed=610, N=6, n_v=9, n_s=7, n_t=5, n_e=3, n_m=3, light=True, t_f=1.0)
+    t["v0"] = 1.0
+    t["lights"] = [(2, 30.0, 10.0, 0.0)]
+    r = oracle.solve(t)
+    assert r["u0"] == -1
+    plan = Plan([t], store_all=True)
+    plan.solve()
+    torch.cuda.synchronize()
+    assert int(plan.u0.cpu()[0]) == -1
+    g5, ds = plan.adjoint_spat()
+    torch.cuda.synchronize()
+    ao = oracle.adjoint(t, r["J"].astype(np.float32).astype(np.float64), r["pi"], r["u0"])
+    assert np.all(np.isnan(ao["dspat"])) and np.all(np.isnan(ds[0].cpu().numpy()))
+    assert np.all(np.isnan(g5.cpu().numpy()))
+    with pytest.raises(DPError):
+        Plan([t]).adjoint_spat()
