@@ -445,9 +445,9 @@ def test_signal_timing_sensitivities_match_oracle(torch):
 
 def test_signal_timing_sensitivities_edge_cases(torch):
     """No admissible control from x0 (every first step outlasts a 1 s time
-    grid): the oracle and dp_adjoint_spat both give not-a-number for every
-    signal, like the theta gradient; a plan without the stored value slabs is
-    refused (DP_ESTATE)."""
+    grid): the oracle, dp_adjoint_spat and dp_adjoint_grade give
+    not-a-number for every signal and every step, like the theta gradient; a
+    plan without the stored value slabs is refused (DP_ESTATE)."""
     from paper_2104_01284_amd._lib import DPError
     t = ins.tiny(seed=610, N=6, n_v=9, n_s=7, n_t=5, n_e=3, n_m=3, light=True, t_f=1.0)
     t["v0"] = 1.0
@@ -463,5 +463,9 @@ def test_signal_timing_sensitivities_edge_cases(torch):
     ao = oracle.adjoint(t, r["J"].astype(np.float32).astype(np.float64), r["pi"], r["u0"])
     assert np.all(np.isnan(ao["dspat"])) and np.all(np.isnan(ds[0].cpu().numpy()))
     assert np.all(np.isnan(g5.cpu().numpy()))
+    g5b, dg = plan.adjoint_grade()
+    torch.cuda.synchronize()
+    assert np.all(np.isnan(ao["dgrade"])) and np.all(np.isnan(dg[0].cpu().numpy()))
+    assert np.all(np.isnan(g5b.cpu().numpy()))
     with pytest.raises(DPError):
         Plan([t]).adjoint_spat()
