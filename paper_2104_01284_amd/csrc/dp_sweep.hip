@@ -409,8 +409,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     const int sh = wlo - wbase;
     // A tile of more than 8 rows runs on JT / 8 groups of waves, group g
     // taking rows 8 g ... 8 g + 7 of the tile: the groups share one staged
-    // window (2H + 1 rows fewer per tile row than separate workgroups) and
-    // each wave keeps the registers of an 8-row tile.  A wave covers 63
+    // window (for a 16-row tile 2H + 1 fewer staged rows than two 8-row
+    // workgroups) and each wave keeps the registers of an 8-row tile.  A wave covers 63
     // consecutive time nodes of its group's rows (its last lane is the halo
     // of the time lerp).
     constexpr int R = JT > 8 ? 8 : JT;          // tile rows per wave
