@@ -190,7 +190,7 @@ def main():
         args.steps = {"plain": 1000, "paper": 200, "realistic": 50, "batched": 10, "large": 5,
                       "mpc": 300}[args.workload]
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
+        print(f"bench.py measures one GPU: the solver has no multi-GPU path (asked for {args.gpus}); "
               f"run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
