@@ -71,6 +71,7 @@ def _load():
     lib.or_root.argtypes = [ins, d, d, i32, d]
     lib.or_solve.argtypes = [ins, d, i16, d, d, i32]
     lib.or_rollout.argtypes = [ins, i16, C.c_int32, d, i32]
+    lib.or_policy_lookup.argtypes = [ins, i16, C.c_double, C.c_double, C.c_double, i32]
     lib.or_tangent.argtypes = [ins, d, i16, C.c_int32, d]
     lib.or_adjoint.argtypes = [ins, d, i16, C.c_int32, d, d, d, d, d, d, d, d, d]
     lib.or_count_evals.argtypes = [ins]
@@ -232,6 +233,17 @@ def rollout(inst, pi, u0):
     viol = C.c_int32()
     st = _load().or_rollout(I.ref, _ptr(pi, C.c_int16), int(u0), _ptr(traj, C.c_double), C.byref(viol))
     return {"status": st, "violations": viol.value, "traj": traj.reshape(I.N + 1, 8)}
+
+
+def policy_lookup(inst, pik, v, xi, t):
+    """The rollout's control at the off-grid state (v, xi, t) from one
+    stage's policy slab: (u, out_of_grid)."""
+    I = _as_inst(inst)
+    pik = np.ascontiguousarray(pik, dtype=np.int16).ravel()
+    assert pik.size == I.S
+    oog = C.c_int32()
+    u = _load().or_policy_lookup(I.ref, _ptr(pik, C.c_int16), float(v), float(xi), float(t), C.byref(oog))
+    return int(u), int(oog.value)
 
 
 def tangent(inst, J, pi, u0):

@@ -534,6 +534,15 @@ static int policy_lookup(const or_inst *I, const int16_t *pik, double v, double 
     return bu;
 }
 
+/* The rollout's control lookup at an off-grid state, for its pin. */
+int or_policy_lookup(const or_inst *I, const int16_t *pik, double v, double xi, double t, int32_t *out_of_grid)
+{
+    int oog = 0;
+    const int u = policy_lookup(I, pik, v, xi, t, &oog);
+    *out_of_grid = oog;
+    return u;
+}
+
 /* traj row k = {v, xi, t, u, T_eng, T_mot, fuel so far, cost so far}; the
  * last row's cost includes the terminal cost. */
 int or_rollout(const or_inst *I, const int16_t *pi_all, int32_t u0, double *traj, int32_t *viol)

@@ -78,6 +78,13 @@ void or_root(const or_inst *I, const double *J1, double *V0, int32_t *u0, double
 void or_solve(const or_inst *I, double *J_all, int16_t *pi_all, double *q2_all,
               double *V0, int32_t *u0);
 
+/* The rollout's control at an off-grid state (v, xi, t) from one stage's
+ * policy slab: among the bracketing nodes of positive interpolation weight
+ * whose policy is a control (>= 0), the one of largest weight, equal weights
+ * to the lowest linear node index; -1 if none.  Coordinates outside the grid
+ * are clamped to it and set *out_of_grid. */
+int or_policy_lookup(const or_inst *I, const int16_t *pik, double v, double xi, double t, int32_t *out_of_grid);
+
 /* Forward rollout of the stored policy; traj [(N+1)*8]; returns status
  * (0 ok, -4 no admissible control); *viol counts exact-state violations. */
 int or_rollout(const or_inst *I, const int16_t *pi_all, int32_t u0, double *traj, int32_t *viol);

@@ -463,7 +463,12 @@ def test_tangent_adjoint_fd_and_identities():
     dV/dw_soc the expected terminal (xi - xi_ref)^2; the occupancy sums to one
     and reproduces V_0; central finite differences of fresh solves agree at
     policy-stable points."""
-    inst = ins.plain()
+    tangent_adjoint_fd_identities(ins.plain(), range(5))
+
+
+def tangent_adjoint_fd_identities(inst, params):
+    """The checks of test_tangent_adjoint_fd_and_identities on `inst`, with
+    finite differences for the parameters `params` (theta indices)."""
     r = oracle.solve(inst)
     tg = oracle.tangent(inst, r["J"], r["pi"], r["u0"])
     ad = oracle.adjoint(inst, r["J"], r["pi"], r["u0"])
@@ -477,7 +482,7 @@ def test_tangent_adjoint_fd_and_identities():
     # 1e-6) until no argmin on the occupancy support changes between the two
     # perturbed solves; then fresh-solve differences must equal the tangent
     checked = 0
-    for p in range(5):
+    for p in params:
         for rel in (1e-4, 1e-5, 1e-6):
             h = rel * abs(inst["theta"][p])
             stable, fd = _policy_stable(inst, inst["theta"], h, p)
@@ -485,7 +490,7 @@ def test_tangent_adjoint_fd_and_identities():
                 assert fd == pytest.approx(tg[p], rel=1e-6, abs=1e-12), (p, rel)
                 checked += 1
                 break
-    assert checked == 5
+    assert checked == len(params)
 
 
 # ---------------------------------------------------------------- rollout --
@@ -689,3 +694,51 @@ def test_signal_timing_sensitivities_without_waits():
     assert r["u0"] >= 0 and len(inst["lights"]) == 1
     ad = oracle.adjoint(inst, r["J"], r["pi"], r["u0"])
     assert ad["dspat"].shape == (1, 3) and np.all(ad["dspat"] == 0.0)
+
+
+def test_rollout_policy_lookup_nearest_corner():
+    """The rollout's control at an off-grid state (C18 reading): among the
+    eight bracketing nodes of positive trilinear weight whose policy is a
+    control, the one of largest weight; equal weights go to the lowest linear
+    node index; nodes holding -1 or -2 are passed over.  Grids with binary
+    steps (h_v = 1, h_xi = 0.25, h_t = 1) make every weight exact, and the
+    expected node is written out from the weights by hand."""
+    inst = ins.tiny(seed=700, N=2, n_v=5, n_s=3, n_t=9, n_e=3, n_m=3, light=False, t_f=8.0)
+    inst["v_grid"] = (0.0, 4.0, 5)
+    inst["soc_grid"] = (0.25, 0.75, 3)
+    I = oracle.Instance(inst)
+    nv, ns, nt = I.shape
+    pik = (np.arange(nv * ns * nt) % 997).astype(np.int16).reshape(nv, ns, nt)
+
+    def node(i, j, m):
+        return int(pik[i, j, m])
+
+    # r = (1.25, 0.75, 2.625): v weights .75/.25 (nodes 1, 2), xi .25/.75
+    # (nodes 0, 1), t .375/.625 (nodes 2, 3); the largest is (1, 1, 3)
+    v, xi, t = 1.25, 0.25 + 0.25 * 0.75, 2.625
+    assert oracle.policy_lookup(I, pik, v, xi, t) == (node(1, 1, 3), 0)
+    # without a control there: the next largest weight is (1, 1, 2)
+    # (.75 .75 .375 against .75 .25 .625 and .25 .75 .625)
+    for code in (-1, -2):
+        p2 = pik.copy()
+        p2[1, 1, 3] = code
+        assert oracle.policy_lookup(I, p2, v, xi, t) == (node(1, 1, 2), 0)
+    # a tie: r = (1.5, 1, 3) leaves (1, 1, 3) and (2, 1, 3) at weight .5
+    # (xi and t on nodes: the upper corners weigh 0); the lower index wins,
+    # the other when the first holds no control
+    assert oracle.policy_lookup(I, pik, 1.5, 0.5, 3.0) == (node(1, 1, 3), 0)
+    p3 = pik.copy()
+    p3[1, 1, 3] = -1
+    assert oracle.policy_lookup(I, p3, 1.5, 0.5, 3.0) == (node(2, 1, 3), 0)
+    # a zero-weight corner never decides, even as the only control left
+    p4 = np.full_like(pik, -1)
+    p4[2, 2, 4] = 5                       # weight 0 at r = (1.5, 1, 3)
+    assert oracle.policy_lookup(I, p4, 1.5, 0.5, 3.0) == (-1, 0)
+    p4[2, 1, 3] = 6
+    assert oracle.policy_lookup(I, p4, 1.5, 0.5, 3.0) == (6, 0)
+    # the top edge of a grid is the upper node of the last cell
+    assert oracle.policy_lookup(I, pik, 4.0, 0.75, 8.0) == (node(4, 2, 8), 0)
+    # outside the grid: clamped onto it, and flagged
+    assert oracle.policy_lookup(I, pik, 5.0, 0.5, 3.0) == (node(4, 1, 3), 1)
+    assert oracle.policy_lookup(I, pik, 1.0, 0.5, -0.5) == (node(1, 1, 0), 1)
+
