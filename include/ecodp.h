@@ -235,6 +235,27 @@ int dp_adjoint_grade(dp_plan *p, const void *J, const void *pi, const int16_t *u
 int dp_adjoint_spat(dp_plan *p, const void *J, const void *pi, const int16_t *u0_dev,
                     void *scratch, double *grad_dev, double *dspat_dev, void *stream);
 
+/* State-control evaluations the state sweep executed for each instance
+ * since the start of the last dp_solve (plus those of dp_stage calls made
+ * after it): counts[inst] for every instance of the plan, a host array.
+ * The grouped sweep counts, per (speed node, SoC tile), the controls it
+ * visits with at least one admissible successor row in the tile, times the
+ * tile's rows and the time nodes (nodes above the stage's speed limit and
+ * controls infeasible for the whole row are skipped, Eq. 7a-d); the simple
+ * sweep counts the admissible (speed node, control) pairs times all SoC and
+ * time nodes.  dp_instance_info.evaluations is the dense count (every node
+ * times every control) that the throughput figures use.  Synchronises on
+ * `stream`. */
+int dp_executed_evaluations(dp_plan *p, int64_t *counts, void *stream);
+
+/* Synchronises on `stream` and reads the plan's device error word, which
+ * kernels set when they meet a condition the host checks could not exclude
+ * (a SoC cell offset outside the int8 field of the sweep's records).
+ * DP_OK if it is clear; else DP_EDEVICE with the condition named in
+ * dp_last_error(), and the word is cleared.  Results of the solves enqueued
+ * before such an error are not to be used. */
+int dp_device_check(dp_plan *p, void *stream);
+
 /* With DP_TIMING: total device milliseconds and launch count of the state
  * sweep kernel over every dp_solve / dp_stage since the previous call
  * (synchronises on the recorded events, then starts a new count). */

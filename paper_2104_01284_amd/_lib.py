@@ -21,7 +21,8 @@ DP_GRAPH = 4
 
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_stage",
            "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_adjoint_grade",
-           "dp_adjoint_spat", "dp_sweep_time", "dp_destroy", "dp_status_string", "dp_last_error")
+           "dp_adjoint_spat", "dp_executed_evaluations", "dp_device_check", "dp_sweep_time", "dp_destroy",
+           "dp_status_string", "dp_last_error")
 
 
 class DpProblemDesc(C.Structure):
@@ -83,6 +84,8 @@ def load(require_torch: bool = True):
     lib.dp_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dp_adjoint_grade.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.dp_adjoint_spat.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.dp_executed_evaluations.argtypes = [vp, C.POINTER(C.c_int64), vp]
+    lib.dp_device_check.argtypes = [vp, vp]
     lib.dp_sweep_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     lib.dp_destroy.argtypes = [vp]
     lib.dp_destroy.restype = None

@@ -280,4 +280,17 @@ class Plan:
         return ms.value, n.value
 
     def evaluations(self) -> int:
+        """Dense state-control evaluations of one solve of every instance."""
         return int(sum(int(i.evaluations) for i in self.info))
+
+    def executed_evaluations(self):
+        """Evaluations the state sweep executed per instance since the last
+        solve began (synchronises the current stream)."""
+        out = (C.c_int64 * self.n)()
+        L.check(self.lib.dp_executed_evaluations(self._h, out, self._stream()), "dp_executed_evaluations")
+        return [int(x) for x in out]
+
+    def device_check(self):
+        """Raise DPError if a kernel set the plan's device error word
+        (synchronises the current stream)."""
+        L.check(self.lib.dp_device_check(self._h, self._stream()), "dp_device_check")

@@ -110,6 +110,8 @@ struct dp_plan {
     DevInst *dev_insts = nullptr;
     StageJob *dev_jobs = nullptr;
     int *dev_ib = nullptr;
+    int *dev_err = nullptr;                  // device error word (kDevErr* bits), sticky until read
+    unsigned long long *dev_count = nullptr; // per instance: evaluations executed since the last solve began
     size_t scr_q = 0;                // 8 queue counters per sweep launch, then 8 for dp_stage
     size_t scr_gpart = 0;            // adjoint partial gradient sums
     size_t scr_gstage = 0;           // adjoint per-stage C_rr shares (grade sensitivities)
@@ -255,7 +257,7 @@ int soc_shift_bound(const DevInst &P, const dp_problem_desc &d)
     const double cosa = 1.0 / std::sqrt(1.0 + gmax * gmax), sina = gmax * cosa;
     const double xis[2] = {d.soc_lo, d.soc_hi};
     double smax = 0.0;
-    for (int i = 1; i < P.n_v; i++) {
+    for (int i = 0; i < P.n_v; i++) {
         const double v = P.v_lo + i * P.hv;
         if (!(v > 0.0)) continue;
         for (int b = 0; b < P.n_m; b++) {
@@ -483,10 +485,12 @@ static int plan_rounds(dp_plan *p, size_t scr)
     const size_t b_jobs = align_up(sizeof(StageJob) * std::max<size_t>(1, p->jobs.size()), 256);
     const size_t b_ib = align_up(sizeof(int) * std::max<size_t>(1, ib.size()), 256);
     const size_t b_bj = align_up(sizeof(StageJob) * std::max<size_t>(1, p->bjobs.size()), 256);
-    hipError_t e = hipMalloc(&p->dev_tables, b_inst + b_jobs + b_ib + b_bj);
-    if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu table bytes: %s", b_inst + b_jobs + b_ib + b_bj,
-                                     hipGetErrorString(e));
-    std::vector<unsigned char> host(b_inst + b_jobs + b_ib + b_bj, 0);
+    // the error word, then one evaluation counter per instance (zeroed here)
+    const size_t b_cnt = align_up(sizeof(unsigned long long) * (1 + (size_t)n_inst), 256);
+    const size_t b_all = b_inst + b_jobs + b_ib + b_bj + b_cnt;
+    hipError_t e = hipMalloc(&p->dev_tables, b_all);
+    if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu table bytes: %s", b_all, hipGetErrorString(e));
+    std::vector<unsigned char> host(b_all, 0);
     for (int b = 0; b < n_inst; b++) std::memcpy(host.data() + sizeof(DevInst) * b, &p->inst[b].P, sizeof(DevInst));
     if (!p->jobs.empty()) std::memcpy(host.data() + b_inst, p->jobs.data(), sizeof(StageJob) * p->jobs.size());
     if (!ib.empty()) std::memcpy(host.data() + b_inst + b_jobs, ib.data(), sizeof(int) * ib.size());
@@ -497,6 +501,8 @@ static int plan_rounds(dp_plan *p, size_t scr)
     p->dev_jobs = (StageJob *)(d + b_inst);
     p->dev_ib = (int *)(d + b_inst + b_jobs);
     p->dev_bjobs = (StageJob *)(d + b_inst + b_jobs + b_ib);
+    p->dev_err = (int *)(d + b_inst + b_jobs + b_ib + b_bj);
+    p->dev_count = (unsigned long long *)(d + b_inst + b_jobs + b_ib + b_bj) + 1;
     if ((e = hipMemcpy(p->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "table upload");
     return DP_OK;
@@ -923,6 +929,8 @@ static StageBase stage_base(dp_plan *p, void *J, void *pi, void *scratch)
     B.Jn = nullptr;
     B.Jk = nullptr;
     B.pik = nullptr;
+    B.count = p->dev_count;
+    B.err = p->dev_err;
     return B;
 }
 
@@ -934,7 +942,8 @@ static int enqueue_simple(dp_plan *p, const Inst &I, int k, const float *Jn, flo
     BatEntry *bat = (BatEntry *)((char *)scratch + I.scr_bat);
     const int L = I.light_of_stage[k];
     const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
-    if (launch_stage_table(I.P, k, st, bat, s)) return hip_fail(hipGetLastError(), "stage table launch");
+    if (launch_stage_table(I.P, k, st, bat, p->dev_count + (&I - p->inst.data()), s))
+        return hip_fail(hipGetLastError(), "stage table launch");
     int rc = time_begin(p, s);
     if (rc) return rc;
     if (launch_sweep(I.P, k, Jn, Jk, pik, st, bat, tl, s)) return hip_fail(hipGetLastError(), "sweep launch");
@@ -954,8 +963,9 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
         const Inst &I = p->inst[b];
         if (launch_terminal(I.P, slab_ptr(p, I, J, I.N), s)) return hip_fail(hipGetLastError(), "terminal launch");
     }
-    if (launch_fill_i32(queue_slot(p, scratch, 0), 8L * p->n_q_slots, 0, s))
-        return hip_fail(hipGetLastError(), "queue reset launch");
+    if (launch_fill_i32(queue_slot(p, scratch, 0), 8L * p->n_q_slots, 0, s) ||
+        launch_fill_i32((int *)p->dev_count, 2L * (long)p->inst.size(), 0, s))
+        return hip_fail(hipGetLastError(), "counter reset launch");
     const StageBase base = stage_base(p, J, pi, scratch);
     bool pre = false;   // this round's grouped-sweep tables were launched on the table stream
     for (size_t r = 0; r < p->rounds.size(); r++) {
@@ -1273,6 +1283,39 @@ int dp_adjoint_spat(dp_plan *p, const void *J, const void *pi, const int16_t *u0
 {
     if (!dspat_dev) return fail(DP_EINVAL, "NULL signal-timing sensitivity buffer");
     return adjoint_impl(p, J, pi, u0_dev, scratch, grad_dev, nullptr, dspat_dev, stream);
+}
+
+int dp_executed_evaluations(dp_plan *p, int64_t *counts, void *stream)
+{
+    if (!p || !counts) return fail(DP_EINVAL, "NULL argument");
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<unsigned long long> h(p->inst.size());
+    e = hipMemcpyAsync(h.data(), p->dev_count, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "evaluation counters");
+    for (size_t b = 0; b < h.size(); b++) counts[b] = (int64_t)h[b];
+    return DP_OK;
+}
+
+int dp_device_check(dp_plan *p, void *stream)
+{
+    if (!p) return fail(DP_EINVAL, "plan is NULL");
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    int w = 0;
+    e = hipMemcpyAsync(&w, p->dev_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "device error word");
+    if (w == 0) return DP_OK;
+    const int zero = 0;
+    e = hipMemcpyAsync(p->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "device error word reset");
+    return fail(DP_EDEVICE, "device error word 0x%x:%s", w,
+                (w & kDevErrCellOffset) ? " a SoC cell offset did not fit its int8 record field" : "");
 }
 
 int dp_sweep_time(dp_plan *p, double *ms, int32_t *launches)

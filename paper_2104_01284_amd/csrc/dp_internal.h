@@ -10,7 +10,8 @@ namespace ecodp {
 int launch_terminal(const DevInst &P, float *JN, hipStream_t s);
 int launch_terminal_shift(const float *src, long nvs, int n_src, double h_src, double t_shift, int n_dst, double h_dst,
                           double Jinf, float *dst, hipStream_t s);
-int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, hipStream_t s);
+int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, unsigned long long *count,
+                       hipStream_t s);
 int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const StageEntry *st,
                  const BatEntry *bat, const TLEntry *tl, hipStream_t s);
 int launch_root(const DevInst *Pdev, const float *J1, float *V0, int16_t *u0, hipStream_t s);

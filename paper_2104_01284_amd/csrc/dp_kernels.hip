@@ -71,7 +71,8 @@ int launch_terminal_shift(const float *src, long nvs, int n_src, double h_src, d
 // One thread per (speed node i, control u, SoC node j), j fastest.  The
 // powertrain part (speed and time coordinates, stage cost) is written once
 // per (i, u) by the j == 0 thread; every thread writes its battery coordinate.
-__global__ void k_stage_table(DevInst P, int k, StageEntry *__restrict__ st, BatEntry *__restrict__ bat)
+__global__ void k_stage_table(DevInst P, int k, StageEntry *__restrict__ st, BatEntry *__restrict__ bat,
+                              unsigned long long *__restrict__ count)
 {
 #pragma clang fp contract(off)
     const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -99,6 +100,11 @@ __global__ void k_stage_table(DevInst P, int k, StageEntry *__restrict__ st, Bat
             ft = delta - fl;
         }
     }
+    // the simple sweep evaluates every node of a feasible pair (speed node
+    // under the stage's limit) and skips the others: count those evaluations
+    const unsigned long long counted = __ballot(j == 0 && ok && !(v > P.vmax[k]));
+    if ((threadIdx.x & 63) == 0 && counted)
+        atomicAdd(count, (unsigned long long)__popcll(counted) * (unsigned long long)P.n_s * P.n_t);
     if (j == 0) {
         StageEntry e;
         e.c = (float)p.cost;
@@ -322,11 +328,12 @@ int launch_terminal(const DevInst &P, float *JN, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, hipStream_t s)
+int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, unsigned long long *count,
+                       hipStream_t s)
 {
     const long total = (long)P.n_v * P.n_u * P.n_s;
     const int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_stage_table, dim3(blocks), dim3(256), 0, s, P, k, st, bat);
+    hipLaunchKernelGGL(k_stage_table, dim3(blocks), dim3(256), 0, s, P, k, st, bat, count);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -109,7 +109,12 @@ struct StageBase {
     const float *Jn;
     float *Jk;
     int16_t *pik;
+    unsigned long long *count;   // per instance: state-control evaluations the sweep executed
+    int *err;                    // plan's device error word (kDevErr* bits)
 };
+
+// Bits of the plan's device error word (sticky until read by the host).
+constexpr int kDevErrCellOffset = 1;   // a SoC cell offset did not fit the records' int8 field
 
 // Result of the continuous one-step model for (stage k, speed v, control).
 struct PT {

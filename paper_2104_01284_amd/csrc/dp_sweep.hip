@@ -222,6 +222,13 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
             const double rs = (double)j - (pd.y * I) / (P.Cnom * P.hs);
             if (rs >= 0.0 && rs <= P.n_s - 1) cell_of(rs, P.n_s, jx, fx);
         }
+        // the row's cell is stored as an int8 offset from the row (the host
+        // bound on the shift keeps it within +-121); one outside that range
+        // would wrap, so it raises the plan's device error instead
+        if (jx >= 0 && (jx - j > 126 || jx - j < -127)) {
+            atomicOr(B.err, kDevErrCellOffset);
+            jx = -1;
+        }
     }
     // The record is regular when its feasible rows have consecutive cells
     // jx = b + q with |b - j0| <= H and the tile holds at least half of JT
@@ -443,6 +450,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     float *chunk = lds + 2 * slot_sz;             // kPrefetch * blockDim floats
     const int cc = __builtin_amdgcn_readfirstlane((kPrefetch * (int)blockDim.x) / CW);   // controls per staged run
     const float *recs = rec + ((long)i * ntiles + tile) * nu * CW;
+    int nrec = 0;   // records of this item with at least one successor (evaluated)
     int plane[2] = {-1, -1};
     int cur_p = -2;
     int SA = 0, SB = 0;   // LDS float offsets of the staged planes cur_p, cur_p + 1
@@ -481,6 +489,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             const int p = __builtin_amdgcn_readfirstlane(__float_as_int(ce[5]));
             const int hdr = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
             if (hdr == kRecEmpty) continue;          // no row of this tile has a successor
+            nrec++;
             if (p != cur_p) {
                 // stage planes p and p+1 (SoC rows wlo..whi, every time node),
                 // keeping a plane already resident from the previous group
@@ -628,6 +637,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             }
         }
     }
+    if (threadIdx.x == 0 && nrec > 0)
+        atomicAdd(B.count + jb.inst, (unsigned long long)nrec * (unsigned long long)(jc * nt));
     if (out_lane && nsplit > 1) {
         // partial minimum of this control slice; the combine kernel finishes
         const long plane_nodes = (long)P.n_v * SV;

@@ -30,6 +30,8 @@ grid sizes of the workloads the method is measured on.
 from __future__ import annotations
 
 import copy
+import hashlib
+
 import numpy as np
 
 KONST_NAMES = ("g", "rho_air", "r_w", "i_g", "eta_dl", "eta_m", "C_nom",
@@ -358,3 +360,17 @@ def evaluations(inst: dict) -> int:
     innermost loop this way)."""
     states = inst["v_grid"][2] * inst["soc_grid"][2] * inst["t_grid"][2]
     return int(inst["N"]) * states * inst["te_grid"][2] * inst["tm_grid"][2]
+
+
+def digest(inst: dict) -> str:
+    """Short content hash of an instance (every field, in key order): stored
+    values written from an instance carry it, and a reader compares it with
+    the hash of today's generator output before using them."""
+    h = hashlib.sha256()
+    for k in sorted(inst):
+        v = inst[k]
+        if isinstance(v, np.ndarray):
+            h.update(k.encode() + v.tobytes())
+        else:
+            h.update(k.encode() + repr(v).encode())
+    return h.hexdigest()[:16]

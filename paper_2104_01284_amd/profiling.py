@@ -11,6 +11,9 @@
       per dispatch), each scaled by what the same counter reads for a plain
       device copy of copy_MiB MiB; prints a summary whose last line is
       machine-readable.
+
+It also reads the stored FP64 oracle results of the parity goldens
+(load_golden, golden_report) for the per-result errors the benchmark reports.
 """
 import hashlib
 import os
@@ -99,6 +102,86 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib, needle, 
         print(f"{name.split('(')[0][:60]:60s} dispatches={n:5d} FETCH={fk:12.1f} KiB WRITE={wk:12.1f} KiB "
               f"-> HBM bytes/dispatch {b:.4e}")
     print(f"traffic_bytes_per_launch={tot:.6e} sweep_source={sweep_source_hash()} split={split}")
+
+
+GOLDEN_DIR = os.path.join(os.path.dirname(HERE), "tests", "golden")
+
+
+def load_golden(name, inst):
+    """Stored FP64 oracle results of workload `name` (written by
+    tests/golden/make_golden.py), or None when there are none or their
+    instance digest differs from `inst`'s (stale for today's generator)."""
+    import json
+    from . import instances
+    path = os.path.join(GOLDEN_DIR, f"{name}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    return g if g.get("digest") == instances.digest(inst) else None
+
+
+def _rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+def golden_report(g, V0, J_all=None, pi_all=None, traj=None, grad=None, band=1e-4):
+    """Errors of one solve's results against stored FP64 oracle results `g`.
+
+    V0: the solve's V_0.  J_all [N+1, n_v, n_soc, n_t] and pi_all [N, ...]:
+    its stored values and policy (device tensors), compared at the stored
+    sample nodes: J relative error (to max(1, |J_64|)); policy mismatches,
+    counted all together, where the FP64 gap between the best and second-best
+    candidate is at least 1e-6 (the absolute reading) or 1e-6 max(1, |J_64|)
+    (the relative reading) or `band` max(1, |J_64|); and the FP64 regret
+    Q_64(u) - J_64 of every mismatching choice u from the stored near-tie
+    list (a choice outside it regrets more than the list's bound).  traj:
+    the rollout rows [N+1, 8] (fuel and time of the last row against the
+    oracle's rollout of its own policy); grad: dV_0/dtheta [5] against the
+    oracle's adjoint on its own solve."""
+    out = {"V0_rel_err": abs(float(V0) - g["V0"]) / abs(g["V0"])}
+    if J_all is not None and g.get("samples"):
+        import torch
+        s = g["samples"]
+        idx = [torch.as_tensor([row[q] for row in s], device=J_all.device) for q in range(4)]
+        Jg = J_all[idx[0], idx[1], idx[2], idx[3]].double().cpu().tolist()
+        pg = pi_all[idx[0], idx[1], idx[2], idx[3]].cpu().tolist()
+        jerr = 0.0
+        mism = lit = relr = inband = beyond = 0
+        regret = regret_rel = 0.0
+        lim = g.get("near_tie", 1e-3)
+        for row, Jv, pv in zip(s, Jg, pg):
+            _, _, _, _, J64, p64, q2, ties = row
+            jerr = max(jerr, _rel(Jv, J64))
+            if pv == p64:
+                continue
+            mism += 1
+            gap = q2 - J64
+            sc = max(1.0, abs(J64))
+            lit += gap >= 1e-6
+            relr += gap >= 1e-6 * sc
+            inband += gap >= band * sc
+            q = dict((u, Q) for u, Q in ties).get(pv)
+            if q is None:
+                beyond += 1
+                regret_rel = max(regret_rel, lim)
+            else:
+                regret = max(regret, q - J64)
+                regret_rel = max(regret_rel, (q - J64) / sc)
+        out["samples"] = {"nodes": len(s), "J_max_rel_err": jerr, "policy_mismatch": mism,
+                          "mismatch_gap_ge_1e-6_abs": lit, "mismatch_gap_ge_1e-6_rel": relr,
+                          f"mismatch_gap_ge_{band:g}_rel": inband, "choice_outside_near_tie_list": beyond,
+                          "max_regret": regret, "max_regret_rel": regret_rel}
+    if traj is not None and "rollout" in g:
+        t = traj[-1].double().cpu().tolist()
+        r = g["rollout"]
+        out["rollout"] = {"fuel_rel_err": abs(t[6] - r["fuel_g"]) / abs(r["fuel_g"]),
+                          "time_rel_err": abs(t[2] - r["time_s"]) / abs(r["time_s"]),
+                          "cost_rel_err": abs(t[7] - r["cost"]) / abs(r["cost"])}
+    if grad is not None and "grad" in g:
+        gg = [float(x) for x in grad]
+        out["grad_rel_err"] = [abs(a - b) / abs(b) if b else abs(a) for a, b in zip(gg, g["grad"])]
+    return out
 
 
 if __name__ == "__main__":

@@ -1,10 +1,22 @@
 """Write the stored oracle values used by the GPU parity tests at full size.
 
 Calls only the FP64 oracle and the seeded instance generator.  Run from the
-repository root:  python tests/golden/make_golden.py [realistic]
-The 2 km instance takes several minutes on 8 host cores.
+repository root:  python tests/golden/make_golden.py [realistic] [large]
+The 2 km instance takes about ten minutes on 6 host threads, the 3 km one
+(1.7e12 evaluations, about 20 GB of host memory for the stored values and
+policy) about two hours.
+
+Each file holds, for the named instance:
+  * the instance digest (instance_digest below), which the tests and the
+    benchmark check before using any stored value;
+  * V_0 and u_0* (Eq. 6), the FP64 rollout totals of the oracle's own policy
+    and the oracle's fixed-policy gradient dV_0/dtheta on its own solve;
+  * sampled nodes (k, i, j, m) of a few stages with J_k, pi_k, the
+    second-best candidate value q2 and the near-tie list: every control whose
+    FP64 candidate value lies within NEAR_TIE max(1, |J_k|) of the best, as
+    (u, Q) pairs, so the FP64 regret of any admissible choice there can be
+    read off without the oracle.
 """
-import hashlib
 import json
 import os
 import sys
@@ -15,39 +27,57 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-import oracle  # noqa: E402
 from paper_2104_01284_amd import instances as ins  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+NEAR_TIE = 1e-3
+
+STAGES = {
+    "realistic": (0, 1, 50, 100, 150, 199),
+    "large": (0, 1, 75, 150, 225, 299),
+}
 
 
 def instance_digest(inst):
-    h = hashlib.sha256()
-    for k in sorted(inst):
-        v = inst[k]
-        if isinstance(v, np.ndarray):
-            h.update(k.encode() + v.tobytes())
-        else:
-            h.update(k.encode() + repr(v).encode())
-    return h.hexdigest()[:16]
+    return ins.digest(inst)
 
 
-def make(name, stages_to_sample=(0, 1, 50, 100, 150, 199), per_stage=256, seed=123):
+def near_ties(I, k, Jn, i, j, m, J, n_u):
+    """Controls whose FP64 candidate is within NEAR_TIE max(1, |J|) of the best."""
+    import oracle
+    if J >= ins.J_INF:
+        return []
+    lim = J + NEAR_TIE * max(1.0, abs(J))
+    out = []
+    for u in list(range(n_u)) + [-2]:
+        q = oracle.node_q(I, k, Jn, i, j, m, u)
+        if q <= lim:
+            out.append([u, q])
+    return out
+
+
+def make(name, per_stage=256, seed=123):
+    import oracle
     inst = ins.make(name)
+    I = oracle.Instance(inst)
     t = time.time()
-    r = oracle.solve(inst, q2=True)
+    r = oracle.solve(I)
     dt = time.time() - t
-    ro = oracle.rollout(inst, r["pi"], r["u0"])
+    print(f"{name}: solve {dt:.1f} s, V0={r['V0']:.9f} u0={r['u0']}", flush=True)
+    ro = oracle.rollout(I, r["pi"], r["u0"])
+    ad = oracle.adjoint(I, r["J"], r["pi"], r["u0"])
     rng = np.random.default_rng(seed)
-    nv, ns, nt = inst["v_grid"][2], inst["soc_grid"][2], inst["t_grid"][2]
+    nv, ns, nt = I.shape
     samples = []
-    for k in stages_to_sample:
+    for k in STAGES[name]:
         if k >= inst["N"]:
             continue
+        Jn = r["J"][k + 1]
         for _ in range(per_stage):
             i, j, m = int(rng.integers(0, nv)), int(rng.integers(0, ns)), int(rng.integers(0, nt))
-            samples.append([k, i, j, m, float(r["J"][k, i, j, m]), int(r["pi"][k, i, j, m]),
-                            float(r["q2"][k, i, j, m])])
+            J, pi, q2 = oracle.node(I, k, Jn, i, j, m)
+            assert J == r["J"][k, i, j, m] and pi == r["pi"][k, i, j, m]
+            samples.append([k, i, j, m, J, pi, q2, near_ties(I, k, Jn, i, j, m, J, I.n_u)])
     out = {
         "source": "oracle.solve (FP64) on paper_2104_01284_amd.instances." + name,
         "instance": inst["name"], "digest": instance_digest(inst),
@@ -56,14 +86,31 @@ def make(name, stages_to_sample=(0, 1, 50, 100, 150, 199), per_stage=256, seed=1
         "rollout": {"status": ro["status"], "violations": ro["violations"],
                     "fuel_g": float(ro["traj"][-1, 6]), "time_s": float(ro["traj"][-1, 2]),
                     "cost": float(ro["traj"][-1, 7])},
+        "grad": [float(x) for x in ad["grad"]],
         "oracle_seconds": dt, "oracle_threads": oracle.num_threads(),
         "evaluations": ins.evaluations(inst),
+        "near_tie": NEAR_TIE,
+        "sample_fields": ["k", "i", "j", "m", "J", "pi", "q2", "near_ties [[u, Q64], ...]"],
         "samples": samples,
     }
     path = os.path.join(HERE, f"{name}_oracle.json")
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1)
-    print(f"wrote {path}: V0={r['V0']:.6f} u0={r['u0']} in {dt:.1f}s")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=0)
+    os.replace(path + ".tmp", path)
+    print(f"wrote {path}: V0={r['V0']:.6f} u0={r['u0']} in {dt:.1f}s", flush=True)
+
+
+def load(name):
+    """The stored file for instance `name` if its digest matches today's
+    generator, else None (reads JSON only)."""
+    path = os.path.join(HERE, f"{name}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    if g.get("digest") != instance_digest(ins.make(name)):
+        return None
+    return g
 
 
 if __name__ == "__main__":

@@ -105,6 +105,9 @@ def test_null_arguments(lib):
     assert lib.dp_adjoint_grade(None, None, None, None, None, None, None, None) == L.DP_EINVAL
     assert lib.dp_adjoint_spat(None, None, None, None, None, None, None, None) == L.DP_EINVAL
     assert lib.dp_set_state(None, 0, 1.0, 0.5, 0.0, None) == L.DP_EINVAL
+    n = (C.c_int64 * 1)()
+    assert lib.dp_executed_evaluations(None, n, None) == L.DP_EINVAL
+    assert lib.dp_device_check(None, None) == L.DP_EINVAL
     a = C.c_size_t()
     assert lib.dp_workspace_size(None, C.byref(a), None, None) == L.DP_EINVAL
     lib.dp_destroy(None)

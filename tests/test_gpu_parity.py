@@ -12,7 +12,6 @@ Tolerances (FP32 values, FP64 coordinates):
   * Rollout (the oracle's policy loaded into the plan): FP64 agreement to 1e-9 relative.
   * Adjoint (the oracle's FP32-rounded J and policy loaded): FP64 agreement to 1e-9 relative.
 """
-import json
 import os
 import sys
 
@@ -23,7 +22,6 @@ import oracle
 from paper_2104_01284_amd import instances as ins
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 REL_J = 4e-6
 REL_GAP = 1e-6
 
@@ -102,8 +100,15 @@ def test_plain_end_to_end(torch):
     say("max end-to-end relative J error", float(err.max()))
     assert err.max() < 1e-4
     pi = plan.policy(0).cpu().numpy()
-    bad, mism, _ = policy_mismatch(pi, r["pi"], r["J"][:-1], r["q2"])
-    say("end-to-end policy mismatches", mism, "outside the near-tie band", bad)
+    bad, mism, abs_bad = policy_mismatch(pi, r["pi"], r["J"][:-1], r["q2"])
+    # end to end the GPU's J_{k+1} carries its own FP32 rounding (up to the
+    # J error above), so near-ties up to that size may flip: every mismatch
+    # must sit where the oracle's FP64 gap is below 1e-4 max(1, |J|)
+    gap = r["q2"] - r["J"][:-1]
+    e2e_bad = int(((pi != r["pi"]) & ~(gap < 1e-4 * np.maximum(1.0, np.abs(r["J"][:-1])))).sum())
+    say("end-to-end policy mismatches", mism, "gap >= 1e-6 rel", bad, "gap >= 1e-6 abs", abs_bad,
+        "gap >= 1e-4 rel", e2e_bad)
+    assert e2e_bad == 0
 
 
 @pytest.mark.parametrize("kernel,tile", [(1, 0), (2, 4), (2, 8), (2, 16)])
@@ -266,29 +271,47 @@ def test_multi_instance_plan_equals_single(torch):
         assert torch.equal(big.policy(b), one.policy(0))
 
 
-@pytest.mark.parametrize("tile", [0, 16])
-def test_realistic_against_golden(torch, tile):
-    path = os.path.join(GOLDEN, "realistic_oracle.json")
-    if not os.path.exists(path):
-        pytest.skip("golden file not generated")
-    with open(path) as f:
-        g = json.load(f)
-    inst = ins.realistic()
-    say("realistic_2km full solve, tile", tile)
-    plan = Plan([inst], store_all=True, sweep_tile=tile)
+def check_against_golden(torch, name, plan, tag):
+    """A full solve against the stored FP64 oracle results of the same
+    instance (digest-checked): V_0 within 1e-4; J at the sampled nodes of six
+    stages within 1e-4 (the GPU recursion carries its own FP32 values from
+    J_N, so its J_{k+1} differs from the oracle's by the accumulated
+    rounding); the policy there equal to the oracle's except where the FP64
+    gap between the best and second-best candidate is below 1e-4 max(1, |J|),
+    and every choice within the stored near-tie list (FP64 regret below 1e-3
+    max(1, |J|)).  Mismatch counts under the literal 1e-6 readings and the
+    largest regret are printed."""
+    from paper_2104_01284_amd.profiling import golden_report, load_golden
+    inst = plan.instances[0]
+    g = load_golden(name, inst)
+    if g is None:
+        pytest.skip(f"no stored oracle results for {name} matching today's instance")
     V0, u0 = plan.solve()
     torch.cuda.synchronize()
-    Vg = float(V0.cpu()[0])
-    say("V0 gpu", Vg, "oracle", g["V0"], "rel", abs(Vg - g["V0"]) / abs(g["V0"]))
-    assert abs(Vg - g["V0"]) <= 1e-4 * abs(g["V0"])
-    J = plan.values(0)
-    s = np.array(g["samples"])
-    k, i, j, m = (s[:, q].astype(int) for q in range(4))
-    idx = [torch.as_tensor(x, device=J.device) for x in (k, i, j, m)]
-    Jg = J[idx[0], idx[1], idx[2], idx[3]].cpu().numpy().astype(np.float64)
-    err = np.abs(Jg - s[:, 4]) / np.maximum(1.0, np.abs(s[:, 4]))
-    say("sampled end-to-end J max rel error", float(err.max()))
-    assert err.max() < 1e-4
+    r = golden_report(g, float(V0.cpu()[0]), plan.values(0), plan.policy(0))
+    say(tag, "V0 gpu", float(V0.cpu()[0]), "oracle", g["V0"], "report", r)
+    assert r["V0_rel_err"] <= 1e-4
+    smp = r["samples"]
+    assert smp["J_max_rel_err"] < 1e-4, smp
+    assert smp["mismatch_gap_ge_0.0001_rel"] == 0, smp
+    assert smp["choice_outside_near_tie_list"] == 0, smp
+    return r
+
+
+@pytest.mark.parametrize("tile", [0, 16])
+def test_realistic_against_golden(torch, tile):
+    say("realistic_2km full solve against the stored oracle results, tile", tile)
+    plan = Plan([ins.realistic()], store_all=True, sweep_tile=tile)
+    check_against_golden(torch, "realistic", plan, "realistic_2km")
+
+
+def test_large_against_golden(torch):
+    """The 3 km instance in the benchmark's launch configuration (the
+    autotuner's 8-row tiles), whole horizon, against the stored FP64 oracle
+    solve of all 300 stages."""
+    say("large_3km full solve against the stored oracle results")
+    plan = Plan([ins.large()], store_all=True, sweep_tile=8)
+    check_against_golden(torch, "large", plan, "large_3km")
 
 
 @pytest.mark.parametrize("tile", [0, 16])
@@ -308,9 +331,10 @@ def test_realistic_sampled_isolated_stages(torch, tile):
 
 def test_large_last_stages_and_sampled_isolated(torch):
     """The 3 km instance (300 stages, 201x81x401 states) in the benchmark's
-    launch configuration: the last five stages on the full grid against the
-    oracle's own recursion from J_N, and sampled nodes of stages 0, 150 and
-    298 from seeded J_{k+1} slabs."""
+    launch configuration: the last five stages on the full grid, each
+    isolated (values and policy of every node from the same FP32 J_{k+1}) and
+    in the recursion against the oracle's own from J_N, and sampled nodes of
+    stages 0, 150 and 298 from seeded J_{k+1} slabs."""
     inst = ins.large()
     N = inst["N"]
     plan = Plan([inst], store_all=True)
@@ -323,6 +347,10 @@ def test_large_last_stages_and_sampled_isolated(torch):
     assert np.array_equal(JN, Jo.reshape(JN.shape).astype(np.float32).astype(np.float64))
     for k in range(N - 1, N - 6, -1):
         say("large_3km full-grid stage", k)
+        # the stage isolated: both sides from the FP32 rounding of the
+        # oracle's J_{k+1}, every node, values and policy
+        check_stage_isolated(torch, plan, inst, 0, k, Jo.reshape(JN.shape).astype(np.float32), "large_3km")
+        # the recursion: the GPU's own values against the oracle's FP64 ones
         Jo, _, _ = oracle.stage(I, k, Jo)
         Jg = plan.values(0)[k].cpu().numpy().astype(np.float64)
         Jo_ = Jo.reshape(Jg.shape)
