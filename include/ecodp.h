@@ -158,6 +158,23 @@ int dp_instance_info_get(const dp_plan *p, int32_t inst, dp_instance_info *info)
 int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev,
              void *stream);
 
+/* dp_solve without a scratch argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The kernels use a
+ * scratch array of DP_STATIC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends; a plan whose
+ * dp_workspace_size() scratch exceeds it gets DP_EUNSUPPORTED (nothing
+ * enqueued).  The launches are those of dp_solve, enqueued eagerly on
+ * `stream` (a DP_GRAPH plan's graph is neither recorded nor replayed, and
+ * no DP_TIMING events are recorded); the results are bit for bit those of
+ * dp_solve.  Every call on one device shares that array, and it keeps the
+ * last call's contents (the solve clears what must start at zero): calls
+ * that overlap on one device, from any plan or stream, race and must be
+ * ordered by the caller.  Later dp_adjoint / dp_stage calls take their own
+ * scratch buffer as before. */
+#define DP_STATIC_SCRATCH_BYTES (64ull << 20)
+int dp_solve_static(dp_plan *p, void *J, void *pi, float *V0_dev, int16_t *u0_dev, void *stream);
+
 /* One backward step k of instance `inst` from a caller-provided J_{k+1} slab
  * (device float [n_v][n_soc][n_t]) into J_out / pi_out (device slabs, not
  * aliasing J_next), with the configuration dp_solve uses for that stage; the

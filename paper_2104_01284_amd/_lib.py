@@ -19,8 +19,8 @@ DP_STORE_ALL_V = 1
 DP_TIMING = 2
 DP_GRAPH = 4
 
-EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_stage",
-           "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_adjoint_grade",
+EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_solve_static",
+           "dp_stage", "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_adjoint_grade",
            "dp_adjoint_spat", "dp_executed_evaluations", "dp_device_check", "dp_sweep_time", "dp_destroy",
            "dp_status_string", "dp_last_error")
 
@@ -76,6 +76,7 @@ def load(require_torch: bool = True):
     lib.dp_workspace_size.argtypes = [vp, C.POINTER(sz), C.POINTER(sz), C.POINTER(sz)]
     lib.dp_instance_info_get.argtypes = [vp, C.c_int32, C.POINTER(DpInstanceInfo)]
     lib.dp_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.dp_solve_static.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.dp_stage.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
     lib.dp_set_state.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, vp]
     lib.dp_terminal_from_values.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,

@@ -169,6 +169,14 @@ class Plan:
                                   C.c_void_p(self.u0.data_ptr()), self._stream()), "dp_solve")
         return self.V0, self.u0
 
+    def solve_static(self):
+        """dp_solve on the library's own scratch (dp_solve_static: no device
+        allocation; calls on one device must not overlap); returns (V0, u0)."""
+        L.check(self.lib.dp_solve_static(self._h, C.c_void_p(self.J.data_ptr()), C.c_void_p(self.pi.data_ptr()),
+                                         C.c_void_p(self.V0.data_ptr()), C.c_void_p(self.u0.data_ptr()),
+                                         self._stream()), "dp_solve_static")
+        return self.V0, self.u0
+
     def slab_shape(self, b=0):
         i = self.info[b]
         return (int(i.n_v), int(i.n_soc), int(i.n_t))

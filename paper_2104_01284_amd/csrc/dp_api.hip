@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -936,7 +937,7 @@ static StageBase stage_base(dp_plan *p, void *J, void *pi, void *scratch)
 
 // Stage k of an instance on the simple per-node sweep.
 static int enqueue_simple(dp_plan *p, const Inst &I, int k, const float *Jn, float *Jk, int16_t *pik, void *scratch,
-                          hipStream_t s)
+                          hipStream_t s, bool timing = true)
 {
     StageEntry *st = (StageEntry *)((char *)scratch + I.scr_st);
     BatEntry *bat = (BatEntry *)((char *)scratch + I.scr_bat);
@@ -944,10 +945,12 @@ static int enqueue_simple(dp_plan *p, const Inst &I, int k, const float *Jn, flo
     const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
     if (launch_stage_table(I.P, k, st, bat, p->dev_count + (&I - p->inst.data()), s))
         return hip_fail(hipGetLastError(), "stage table launch");
-    int rc = time_begin(p, s);
-    if (rc) return rc;
+    if (timing) {
+        int rc = time_begin(p, s);
+        if (rc) return rc;
+    }
     if (launch_sweep(I.P, k, Jn, Jk, pik, st, bat, tl, s)) return hip_fail(hipGetLastError(), "sweep launch");
-    time_end(p, s);
+    if (timing) time_end(p, s);
     return DP_OK;
 }
 
@@ -957,7 +960,9 @@ static int *queue_slot(dp_plan *p, void *scratch, int slot)
 }
 
 // The terminal slabs, every round of stages, then the exact root step.
-static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev, hipStream_t s)
+// timing = false leaves the DP_TIMING events out (they are created on demand).
+static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev, hipStream_t s,
+                         bool timing = true)
 {
     for (size_t b = 0; b < p->inst.size(); b++) {
         const Inst &I = p->inst[b];
@@ -974,7 +979,7 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
             const Inst &I = p->inst[b];
             const int k = I.N - 1 - (int)r;
             int16_t *pik = (int16_t *)((char *)pi + I.pi_off) + (size_t)k * I.S;
-            int rc = enqueue_simple(p, I, k, slab_ptr(p, I, J, k + 1), slab_ptr(p, I, J, k), pik, scratch, s);
+            int rc = enqueue_simple(p, I, k, slab_ptr(p, I, J, k + 1), slab_ptr(p, I, J, k), pik, scratch, s, timing);
             if (rc) return rc;
         }
         if (R.njobs == 0) continue;
@@ -1008,7 +1013,8 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
         // launches of different kernel classes are independent: without
         // DP_TIMING they run side by side on the plan's streams, so one
         // launch's tail overlaps the next one's start
-        const int nside = (p->flags & DP_TIMING) ? 0 : std::min<int>(dp_plan::kSide, (int)R.sweeps.size() - 1);
+        const bool timed = timing && (p->flags & DP_TIMING);
+        const int nside = timed ? 0 : std::min<int>(dp_plan::kSide, (int)R.sweeps.size() - 1);
         if (nside > 0) {
             hipError_t e = hipEventRecord(p->fork, s);
             for (int q = 0; q < nside && e == hipSuccess; q++) e = hipStreamWaitEvent(p->side[q], p->fork, 0);
@@ -1019,12 +1025,14 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
             hipStream_t ls = (nside > 0 && q % (nside + 1) != 0) ? p->side[q % (nside + 1) - 1] : s;
             StageBase Bs = base;
             Bs.jobs = p->dev_jobs + S.job_begin;
-            int rc = time_begin(p, ls);
-            if (rc) return rc;
+            if (timed) {
+                int rc = time_begin(p, ls);
+                if (rc) return rc;
+            }
             if (launch_sweep_jobs(S.jt, S.pitch, S.threads, Bs, S.njobs, p->dev_ib + S.ib_off, S.items,
                                   queue_slot(p, scratch, S.q_slot), S.grid, S.lds, ls))
                 return hip_fail(hipGetLastError(), "sweep launch");
-            time_end(p, ls);
+            if (timed) time_end(p, ls);
         }
         if (nside > 0) {
             hipError_t e = hipSuccess;
@@ -1091,6 +1099,55 @@ int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_
         for (int q = 0; q < 5; q++) p->graph_key[q] = key[q];
     }
     if ((e = hipGraphLaunch(p->graph_exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    p->solved = true;
+    return DP_OK;
+}
+
+// ------------------------------------------------- solve without allocation --
+
+// Scratch of dp_solve_static, for callers that cannot allocate device memory:
+// a file-scope device array, one copy on every device the library runs on,
+// held until the process ends.  Host code never passes this name to a
+// kernel: its device address comes from hipGetSymbolAddress, looked up once
+// per device with that device current.
+constexpr size_t kStaticScratchBytes = DP_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char static_scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void *g_static_ptr[kMaxDevices] = {};
+
+// Device address of static_scratch on `device` (current).
+static int static_scratch_ptr(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(DP_EUNSUPPORTED, "device %d beyond the static scratch table", device);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(static_scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch address");
+        g_static_ptr[device] = ptr;
+    }
+    *out = g_static_ptr[device];
+    return DP_OK;
+}
+
+int dp_solve_static(dp_plan *p, void *J, void *pi, float *V0_dev, int16_t *u0_dev, void *stream)
+{
+    if (!p) return fail(DP_EINVAL, "plan is NULL");
+    if (!J || !pi || !V0_dev || !u0_dev) return fail(DP_EINVAL, "NULL buffer");
+    if (p->bytes_scratch > kStaticScratchBytes)
+        return fail(DP_EUNSUPPORTED, "plan needs %zu scratch bytes, the static scratch holds %zu", p->bytes_scratch,
+                    kStaticScratchBytes);
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void *scratch = nullptr;
+    int rc = static_scratch_ptr(p->device, &scratch);
+    if (rc) return rc;
+    // the same launches as dp_solve, eagerly (no graph, no timing events);
+    // the queue and evaluation counters are cleared by its first fill kernel
+    rc = enqueue_solve(p, J, pi, scratch, V0_dev, u0_dev, (hipStream_t)stream, false);
+    if (rc) return rc;
     p->solved = true;
     return DP_OK;
 }

@@ -100,6 +100,7 @@ def test_null_arguments(lib):
     assert lib.dp_build_problem(None, 1, None, 0, C.byref(h)) == L.DP_EINVAL
     assert lib.dp_build_problem(None, 1, None, 0, None) == L.DP_EINVAL
     assert lib.dp_solve(None, None, None, None, None, None, None) == L.DP_EINVAL
+    assert lib.dp_solve_static(None, None, None, None, None, None) == L.DP_EINVAL
     assert lib.dp_rollout(None, None, None, None, None, None) == L.DP_EINVAL
     assert lib.dp_adjoint(None, None, None, None, None, None, None) == L.DP_EINVAL
     assert lib.dp_adjoint_grade(None, None, None, None, None, None, None, None) == L.DP_EINVAL
