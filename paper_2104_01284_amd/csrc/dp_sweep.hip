@@ -161,12 +161,19 @@ __global__ void __launch_bounds__(256) k_stage_rank(StageBase B)
     }
 }
 
-// Dwords of one packed record: the sorted entry (c, fv, gv, ft, rt, iv, dtc,
-// u), the tile header, the SoC cells of the tile's rows as int8 offsets from
-// the row (JT / 4 dwords), then the tile's (fx gt, gx gt) pairs.
-__host__ __device__ constexpr int rec_cells(int JT) { return 9; }
-__host__ __device__ constexpr int rec_weights(int JT) { return 9 + JT / 4; }
-__host__ __device__ constexpr int rec_words(int JT) { return 9 + JT / 4 + 2 * JT; }
+// Dwords of one packed record: first the SoC weights of the tile's rows, for
+// each group of R = min(JT, 8) rows the R lower-cell weights gx gt then the R
+// upper-cell weights fx gt (a wave reads its group's 2R weights with one LDS
+// load, lane l taking weight l mod 2R, and broadcasts weight q to all lanes
+// with DPP row_newbcast); then 8 scalars: c, fv, gv, rt, ft, iv | dtc << 16,
+// u | hdr << 16 and one spare (read the same way, lane l taking scalar l); then
+// the SoC cells of the tile's rows as int8 offsets from the row (JT / 4
+// dwords).
+__host__ __device__ constexpr int rec_scalars(int JT) { return 2 * JT; }
+__host__ __device__ constexpr int rec_cells(int JT) { return 2 * JT + 8; }
+__host__ __device__ constexpr int rec_words(int JT) { return 2 * JT + 8 + JT / 4; }
+// Scalar slots
+constexpr int kScC = 0, kScFv = 1, kScGv = 2, kScRt = 3, kScFt = 4, kScIvDtc = 5, kScUHdr = 6;
 // Cell offset of a row without a feasible successor (or past the tile).
 constexpr int kNoCell = -128;
 // Record header (dword 8): the window row (0 .. 2H) of the first successor
@@ -250,15 +257,30 @@ __global__ void __launch_bounds__(256) k_stage_bat_sorted(StageBase B)
     else if (bad == 0 && 2 * jc >= JT && b >= j0 - jb.H && b <= j0 + jb.H) hdr = b - (j0 - jb.H);
     const int CW = rec_words(JT);
     float *out = rec + (((long)i * ntiles + tile) * P.n_u + r) * CW;
-    const int WO = rec_weights(JT);
-    // SoC weights times the time weight gt (rounded once, from FP64)
+    // SoC weights times the time weight gt (rounded once, from FP64), by
+    // groups of R rows: lower-cell weights, then upper-cell weights
+    const int R = JT > 8 ? 8 : JT;
+    const int wg = (q / R) * 2 * R, wr = q % R;
     const float nan = __int_as_float(0x7fc00000);
-    out[WO + 2 * q] = jx >= 0 ? (float)(fx * gt) : nan;
-    out[WO + 2 * q + 1] = jx >= 0 ? (float)((1.0 - fx) * gt) : nan;
+    out[wg + wr] = jx >= 0 ? (float)((1.0 - fx) * gt) : nan;
+    out[wg + R + wr] = jx >= 0 ? (float)(fx * gt) : nan;
     // the row's cell as a byte offset from the row (|offset| <= H + 1 < 127)
     reinterpret_cast<int8_t *>(out + rec_cells(JT))[q] = (int8_t)(jx >= 0 ? jx - (j0 + q) : kNoCell);
-    const float *ef = reinterpret_cast<const float *>(&st[ir]);
-    for (int w = q; w < 9; w += JT) out[w] = w < 8 ? ef[w] : __int_as_float(hdr);
+    const SortedEntry &e = st[ir];
+    for (int w = q; w < 8; w += JT) {
+        float x = 0.0f;
+        switch (w) {
+        case kScC: x = e.c; break;
+        case kScFv: x = e.fv; break;
+        case kScGv: x = e.gv; break;
+        case kScRt: x = e.rt; break;
+        case kScFt: x = e.ft; break;
+        case kScIvDtc: x = __int_as_float((e.iv & 0xffff) | (e.dtc << 16)); break;
+        case kScUHdr: x = __int_as_float((e.u & 0xffff) | (int)((unsigned)hdr << 16)); break;
+        default: break;
+        }
+        out[rec_scalars(JT) + w] = x;
+    }
 }
 
 // ------------------------------------------------------------------ sweep --
@@ -298,23 +320,78 @@ template <> __device__ inline void time_lerp<17>(float (&T)[17], float rt)
 }
 #undef ECODP_TL
 
+// Lane q of every row of 16 lanes broadcast to the whole row (DPP
+// row_newbcast): a record field that lane q holds becomes wave-uniform data
+// in a VGPR without an LDS broadcast read.
+template <int L> __device__ inline float row_bcast(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + L, 0xf, 0xf, false));
+}
+
+// SoC lerp of R rows: Q[q] = W(lane q) T[q] + W(lane R + q) T[q + 1], the
+// weights broadcast from the record VGPR W by DPP.  The products with the
+// lower-cell weights are plain code (the compiler folds the broadcast into a
+// v_mul_f32_dpp); the second terms are one v_fmac_f32_dpp per row here.  W is
+// loaded from LDS, but a register copy of it made by the compiler just before
+// this block would be a VALU write, hence the two wait states before the
+// first DPP read.
+template <int R, int Q0> struct SocLow {
+    static __device__ inline void run(float (&Q)[R], float W, const float (&T)[R + 1])
+    {
+        Q[Q0] = row_bcast<Q0>(W) * T[Q0];
+        SocLow<R, Q0 + 1>::run(Q, W, T);
+    }
+};
+template <int R> struct SocLow<R, R> {
+    static __device__ inline void run(float (&)[R], float, const float (&)[R + 1]) {}
+};
+#define ECODP_SF(q, l) "v_fmac_f32_dpp %" #q ", %[w], %" #l " row_newbcast:" #l " row_mask:0xf bank_mask:0xf\n\t"
+template <int R> __device__ inline void soc_lerp(float (&Q)[R], float W, const float (&T)[R + 1]);
+template <> __device__ inline void soc_lerp<4>(float (&Q)[4], float W, const float (&T)[5])
+{
+    SocLow<4, 0>::run(Q, W, T);
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %[w], %[t1] row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %[w], %[t2] row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %[w], %[t3] row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %[w], %[t4] row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(Q[0]), "+v"(Q[1]), "+v"(Q[2]), "+v"(Q[3])
+        : [w] "v"(W), [t1] "v"(T[1]), [t2] "v"(T[2]), [t3] "v"(T[3]), [t4] "v"(T[4]));
+}
+template <> __device__ inline void soc_lerp<8>(float (&Q)[8], float W, const float (&T)[9])
+{
+    SocLow<8, 0>::run(Q, W, T);
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %[w], %[t1] row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %[w], %[t2] row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %[w], %[t3] row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %[w], %[t4] row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %[w], %[t5] row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, %[w], %[t6] row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, %[w], %[t7] row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, %[w], %[t8] row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
+        : "+v"(Q[0]), "+v"(Q[1]), "+v"(Q[2]), "+v"(Q[3]), "+v"(Q[4]), "+v"(Q[5]), "+v"(Q[6]), "+v"(Q[7])
+        : [w] "v"(W), [t1] "v"(T[1]), [t2] "v"(T[2]), [t3] "v"(T[3]), [t4] "v"(T[4]), [t5] "v"(T[5]),
+          [t6] "v"(T[6]), [t7] "v"(T[7]), [t8] "v"(T[8]));
+}
+#undef ECODP_SF
+
 // Registers per thread that prefetch the next run of control records.
 constexpr int kPrefetch = 4;
 // Rows of a next-stage plane one thread loads per pass when staging.
 constexpr int kStageRows = 8;
-// Most window rows of a prefetched next plane (held in registers).
-constexpr int kPrefRows = 17;
 // Value of the staged columns past the last time node (half the largest
 // float, so that sums of two of them stay finite).
 constexpr float kPad = 1.7014118e38f;
 
 // The job and parameter tables come in as separate read-only arguments so
 // that their fields are loaded through the scalar unit.
+// 16-row tiles run three 8-wave workgroups per CU when a lane holds at most
+// 80 registers (six waves per SIMD): the compiler is held to that.
 template <int JT, int PITCH>
-__global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs,
-                                                    const DevInst *__restrict__ insts, int njobs,
-                                                    const int *__restrict__ item_begin, int total,
-                                                    int *__restrict__ queue)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(JT == 16 ? 6 : 1, 8)))
+k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs, const DevInst *__restrict__ insts, int njobs,
+            const int *__restrict__ item_begin, int total, int *__restrict__ queue)
 {
     extern __shared__ float lds_base[];
     constexpr int CW = rec_words(JT);
@@ -450,20 +527,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
     float *chunk = lds + 2 * slot_sz;             // kPrefetch * blockDim floats
     const int cc = __builtin_amdgcn_readfirstlane((kPrefetch * (int)blockDim.x) / CW);   // controls per staged run
     const float *recs = rec + ((long)i * ntiles + tile) * nu * CW;
+    const int wofs = 2 * R * grp;               // this wave group's weights in a record
+    const int wlane = lane & (2 * R - 1);
+    const int slane = lane & 15;
     int nrec = 0;   // records of this item with at least one successor (evaluated)
     int plane[2] = {-1, -1};
     int cur_p = -2;
     int SA = 0, SB = 0;   // LDS float offsets of the staged planes cur_p, cur_p + 1
-    // Controls come grouped by ascending successor speed cell, so after planes
-    // p, p+1 the next group usually needs p+1, p+2: plane p+2's window rows
-    // are loaded into registers while group p runs (windows of at most
-    // kPrefRows rows).  Only for tiles of at most 8 rows on time grids of at
-    // least 352 nodes: there the staged window of a workgroup of six or more
-    // waves already holds residency to about four waves per SIMD, so the
-    // registers cost no occupancy (on narrower grids they cost a wave).
-    constexpr bool kPref = JT <= 8 && PITCH >= 384;
-    float nxt[kPrefRows];
-    int nxt_p = -1;
 
     float pre[kPrefetch];
     auto fetch = [&](int c0) {
@@ -484,12 +554,29 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
         __syncthreads();
         if (c0 + cc < r_end) fetch(c0 + cc);        // in flight while this run is processed
         const int cn = __builtin_amdgcn_readfirstlane(min(cc, r_end - c0));
+        // each control: one LDS load of the wave's 2R weights (lane l takes
+        // weight l mod 2R) and one of the record's scalars and cells (lane l
+        // takes word l mod 16 after the weights), issued one control ahead
+        float Wn = 0.0f, Sn = 0.0f;
+        if (cn > 0) {
+            Wn = chunk[wofs + wlane];
+            Sn = chunk[rec_scalars(JT) + slane];
+        }
         for (int cr = 0; cr < cn; cr++) {
-            const float *ce = chunk + cr * CW;
-            const int p = __builtin_amdgcn_readfirstlane(__float_as_int(ce[5]));
-            const int hdr = __builtin_amdgcn_readfirstlane(__float_as_int(ce[8]));
+            const float W = Wn, S = Sn;
+            const int ivdtc = __builtin_amdgcn_readlane(__float_as_int(S), kScIvDtc);
+            const int uhdr = __builtin_amdgcn_readlane(__float_as_int(S), kScUHdr);
+            if (cr + 1 < cn) {
+                const float *nx = chunk + (cr + 1) * CW;
+                Wn = nx[wofs + wlane];
+                Sn = nx[rec_scalars(JT) + slane];
+            }
+            const int hdr = uhdr >> 16;
             if (hdr == kRecEmpty) continue;          // no row of this tile has a successor
             nrec++;
+            const int p = ivdtc & 0xffff;
+            const int dtc = ivdtc >> 16;
+            const int u = uhdr & 0xffff;
             if (p != cur_p) {
                 // stage planes p and p+1 (SoC rows wlo..whi, every time node),
                 // keeping a plane already resident from the previous group
@@ -528,42 +615,27 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                         if (need_q) lds[sq * slot_sz + (rr + sh) * PITCH + t] = kPad;
                     }
                 }
-                // plane p+1 from the registers when it was prefetched
-                const bool from_pref = kPref && need_q && nxt_p == p + 1;
-                const bool load_q = need_q && !from_pref;
                 if (t < nt) {
-                    if (from_pref) {
-#pragma unroll
-                        for (int rr = 0; rr < kPrefRows; rr++)
-                            if (rr < nrows) lds[sq * slot_sz + (rr + sh) * PITCH + t] = nxt[rr];
-                    }
                     const float *srcp = Jn + (long)p * SV + (long)wlo * nt + t;
                     const float *srcq = srcp + SV;
-                    if (need_p || load_q)
+                    if (need_p || need_q)
                         for (int r0 = grp * kStageRows; r0 < nrows; r0 += NG * kStageRows) {
                             float va[kStageRows], vb[kStageRows];
 #pragma unroll
                             for (int q = 0; q < kStageRows; q++) {
                                 const long off = (long)min(r0 + q, nrows - 1) * nt;
                                 va[q] = need_p ? srcp[off] : 0.0f;
-                                vb[q] = load_q ? srcq[off] : 0.0f;
+                                vb[q] = need_q ? srcq[off] : 0.0f;
                             }
 #pragma unroll
                             for (int q = 0; q < kStageRows; q++) {
                                 if (r0 + q < nrows) {
                                     if (need_p) lds[sp * slot_sz + (r0 + q + sh) * PITCH + t] = va[q];
-                                    if (load_q) lds[sq * slot_sz + (r0 + q + sh) * PITCH + t] = vb[q];
+                                    if (need_q) lds[sq * slot_sz + (r0 + q + sh) * PITCH + t] = vb[q];
                                 }
                             }
                         }
-                    // the likely next plane, in flight while this group runs
-                    if (kPref && nrows <= kPrefRows && p + 2 < P.n_v) {
-                        const float *srcn = srcq + SV;
-#pragma unroll
-                        for (int rr = 0; rr < kPrefRows; rr++) nxt[rr] = rr < nrows ? srcn[(long)rr * nt] : 0.0f;
-                    }
                 }
-                nxt_p = (kPref && nrows <= kPrefRows && p + 2 < P.n_v) ? p + 2 : -1;
                 plane[sp] = p;
                 plane[sq] = p + 1;
                 SA = sp * slot_sz;
@@ -571,11 +643,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                 cur_p = p;
                 __syncthreads();
             }
-            const float c0f = ce[0], fv = ce[1], gv = ce[2], ft = ce[3], rt = ce[4];
-            const int dtc = __float_as_int(ce[6]);
-            const int u = __float_as_int(ce[7]);
+            // wave-uniform scalars of the control as VGPRs (DPP broadcasts)
+            const float c0f = row_bcast<kScC>(S), fv = row_bcast<kScFv>(S), gv = row_bcast<kScGv>(S);
+            const float rt = row_bcast<kScRt>(S);
             const int pos = m + dtc;
-            const float *wp = ce + rec_weights(JT);
             float Qv[R];
             // a wave group of a 16-row tile with at most half of its rows
             // inside the tile (the last tile of the grid) takes the general
@@ -583,30 +654,28 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
             if (hdr >= 0 && (NG == 1 || 2 * (jc - qb) > R)) {
                 // successor times past the grid read the padding columns
                 const int posc = min(pos, PITCH - 1);
-                const float c = c0f;
                 const int a0 = SA + (hdr + qb) * PITCH + posc;
                 const int b0 = SB + (hdr + qb) * PITCH + posc;
-                const float *w = wp + 2 * qb;
-                // speed lerp on the R+1 SoC rows, then the time lerp with
-                // the neighbouring lane (scaled by 1/gt), then the SoC lerp
-                // per node (weights scaled by gt)
+                // speed lerp on the R+1 SoC rows with the stage cost added
+                // (the time and SoC weights of a node sum to one, so c passes
+                // through both lerps), then the time lerp with the
+                // neighbouring lane (scaled by 1/gt), then the SoC lerp per
+                // node (weights scaled by gt)
                 float T[R + 1];
 #pragma unroll
-                for (int q = 0; q <= R; q++) T[q] = fmaf(fv, lds[b0 + q * PITCH], gv * lds[a0 + q * PITCH]);
+                for (int q = 0; q <= R; q++) T[q] = fmaf(fv, lds[b0 + q * PITCH], fmaf(gv, lds[a0 + q * PITCH], c0f));
                 time_lerp(T, rt);
-#pragma unroll
-                for (int q = 0; q < R; q++) Qv[q] = fmaf(w[2 * q], T[q + 1], fmaf(w[2 * q + 1], T[q], c));
+                soc_lerp<R>(Qv, W, T);
             } else {
+                const float ft = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(S), kScFt));
                 const bool okt = out_lane && (pos < nt - 1 || (pos == nt - 1 && ft == 0.0f));
                 const int posc = min(pos, nt - 1);
-                // lanes whose successor time is off the grid get an infinite
-                // stage cost, so their candidates never win
-                const float c = okt ? c0f : __builtin_inff();
-                // the rows' cells, four int8 offsets per dword (wave-uniform)
+                // the rows' cells, four int8 offsets per dword, held by the
+                // scalar VGPR's lanes 8 ...
                 int cw[R / 4];
 #pragma unroll
                 for (int w = 0; w < R / 4; w++)
-                    cw[w] = __builtin_amdgcn_readfirstlane(__float_as_int(ce[rec_cells(JT) + qb / 4 + w]));
+                    cw[w] = __builtin_amdgcn_readlane(__float_as_int(S), 8 + qb / 4 + w);
 #pragma unroll
                 for (int q = 0; q < R; q++) {
                     const int off = (int)(int8_t)(cw[q / 4] >> (8 * (q % 4)));
@@ -617,15 +686,21 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(StageBase B, const StageJob 
                         if (jx >= wlo && jx + 1 <= whi) {
                             const int a = SA + (jx - wbase) * PITCH + posc;
                             const int b = SB + (jx - wbase) * PITCH + posc;
-                            T2[0] = fmaf(fv, lds[b], gv * lds[a]);
-                            T2[1] = fmaf(fv, lds[b + PITCH], gv * lds[a + PITCH]);
+                            T2[0] = fmaf(fv, lds[b], fmaf(gv, lds[a], c0f));
+                            T2[1] = fmaf(fv, lds[b + PITCH], fmaf(gv, lds[a + PITCH], c0f));
                         } else {
                             const float *a = Jn + (long)p * SV + (long)jx * nt + posc;
-                            T2[0] = fmaf(fv, a[SV], gv * a[0]);
-                            T2[1] = fmaf(fv, a[SV + nt], gv * a[nt]);
+                            T2[0] = fmaf(fv, a[SV], fmaf(gv, a[0], c0f));
+                            T2[1] = fmaf(fv, a[SV + nt], fmaf(gv, a[nt], c0f));
                         }
+                        // (every lane's value stays finite through the time
+                        // lerp, which reads the neighbouring lane's)
                         time_lerp(T2, rt);
-                        Qv[q] = fmaf(wp[2 * (qb + q)], T2[1], fmaf(wp[2 * (qb + q) + 1], T2[0], c));
+                        const float w0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(W), q));
+                        const float w1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(W), R + q));
+                        const float qv = fmaf(w1, T2[1], w0 * T2[0]);
+                        // a lane whose successor time is off the grid never wins
+                        Qv[q] = okt ? qv : __builtin_inff();
                     }
                 }
             }
@@ -746,8 +821,10 @@ int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_record
 
 size_t lds_sweep_bytes(int JT, int H, int n_t)
 {
+    // the record chunk is followed by 16 spare floats: a record's scalar
+    // load reads 16 words after its weights, past the last record's end
     return sizeof(float) * (2 * (size_t)sweep_rows(JT, H) * sweep_pitch(n_t) +
-                            (size_t)kPrefetch * sweep_threads(JT, n_t));
+                            (size_t)kPrefetch * sweep_threads(JT, n_t) + 16);
 }
 
 size_t lds_job_index_bytes(int njobs) { return njobs > 1 ? sizeof(int) * (size_t)(((njobs + 64) / 64) * 64) : 0; }
