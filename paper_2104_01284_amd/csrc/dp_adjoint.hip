@@ -74,14 +74,14 @@ __device__ double interp_f64(const DevInst &P, const float *J, double rv, double
     return acc;
 }
 
-// One thread per instance: x0, the root control u_0*, then at each stage the
-// nearest stored control (or the wait at a red signal), exact FP64 dynamics,
-// fuel, time and cost accumulated in FP64, terminal cost at N.
-__global__ void k_rollout(DevInst P, const int16_t *__restrict__ pi, const int16_t *__restrict__ u0p,
-                          double *__restrict__ traj, int32_t *__restrict__ status)
+// One instance: x0, the root control u_0*, then at each stage the nearest
+// stored control (or the wait at a red signal), exact FP64 dynamics, fuel,
+// time and cost accumulated in FP64, terminal cost at N.  The stages depend
+// on each other, so one thread runs them.
+__device__ void rollout_one(const DevInst &P, const int16_t *__restrict__ pi, const int16_t *__restrict__ u0p,
+                            double *__restrict__ traj, int32_t *__restrict__ status)
 {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const long S = (long)P.n_v * P.n_s * P.n_t;
     double v = P.v0, xi = P.soc0, t = 0.0, fuel = 0.0, cost = 0.0;
     int st = 0, viol = 0;
@@ -159,6 +159,20 @@ __global__ void k_rollout(DevInst P, const int16_t *__restrict__ pi, const int16
     }
     status[0] = st;
     status[1] = viol;
+}
+
+// Every instance of a plan in one launch, one wave per instance (its first
+// lane runs the rollout): policy slabs at byte offsets pi_off[b] from pi,
+// rows at double offsets traj_off[b] from traj.
+__global__ void __launch_bounds__(64) k_rollout_jobs(const DevInst *__restrict__ insts, const char *__restrict__ pi,
+                                                     const long long *__restrict__ pi_off,
+                                                     const long long *__restrict__ traj_off,
+                                                     const int16_t *__restrict__ u0, double *__restrict__ traj,
+                                                     int32_t *__restrict__ status)
+{
+    const int b = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    rollout_one(insts[b], (const int16_t *)(pi + pi_off[b]), u0 + b, traj + traj_off[b], status + 2 * b);
 }
 
 // ------------------------------------------------------------------ adjoint --
@@ -516,12 +530,14 @@ static int grid_for(long n)
     return (int)b;
 }
 
-int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, double *traj, int32_t *status,
-                   hipStream_t s)
+int launch_rollout_jobs(const DevInst *insts, int n_inst, const void *pi, const long long *pi_off,
+                        const long long *traj_off, const int16_t *u0, double *traj, int32_t *status, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rollout, dim3(1), dim3(64), 0, s, P, pi, u0, traj, status);
+    hipLaunchKernelGGL(k_rollout_jobs, dim3(n_inst), dim3(64), 0, s, insts, (const char *)pi, pi_off, traj_off, u0, traj,
+                       status);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
 
 int launch_fill_f64(double *p, long n, double v, hipStream_t s)
 {

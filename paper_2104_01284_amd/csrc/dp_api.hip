@@ -106,6 +106,9 @@ struct dp_plan {
     std::vector<StageJob> jobs;
     std::vector<StageJob> bjobs;     // per round, the jobs that build stage tables
     StageJob *dev_bjobs = nullptr;
+    long long *dev_roll = nullptr;   // per instance [4][n_inst]: pi byte offset, traj double offset,
+                                     // J_1 and J_N byte offsets
+    long max_slab = 0;               // largest slab of any instance
     std::vector<Round> rounds;
     void *dev_tables = nullptr;
     DevInst *dev_insts = nullptr;
@@ -488,7 +491,8 @@ static int plan_rounds(dp_plan *p, size_t scr)
     const size_t b_bj = align_up(sizeof(StageJob) * std::max<size_t>(1, p->bjobs.size()), 256);
     // the error word, then one evaluation counter per instance (zeroed here)
     const size_t b_cnt = align_up(sizeof(unsigned long long) * (1 + (size_t)n_inst), 256);
-    const size_t b_all = b_inst + b_jobs + b_ib + b_bj + b_cnt;
+    const size_t b_roll = align_up(sizeof(long long) * 4 * (size_t)n_inst, 256);
+    const size_t b_all = b_inst + b_jobs + b_ib + b_bj + b_cnt + b_roll;
     hipError_t e = hipMalloc(&p->dev_tables, b_all);
     if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu table bytes: %s", b_all, hipGetErrorString(e));
     std::vector<unsigned char> host(b_all, 0);
@@ -504,6 +508,19 @@ static int plan_rounds(dp_plan *p, size_t scr)
     p->dev_bjobs = (StageJob *)(d + b_inst + b_jobs + b_ib);
     p->dev_err = (int *)(d + b_inst + b_jobs + b_ib + b_bj);
     p->dev_count = (unsigned long long *)(d + b_inst + b_jobs + b_ib + b_bj) + 1;
+    p->dev_roll = (long long *)(d + b_inst + b_jobs + b_ib + b_bj + b_cnt);
+    {
+        long long *roll = (long long *)(host.data() + b_inst + b_jobs + b_ib + b_bj + b_cnt);
+        const bool all = (p->flags & DP_STORE_ALL_V) != 0;
+        for (int b = 0; b < n_inst; b++) {
+            const Inst &I = p->inst[b];
+            roll[b] = (long long)I.pi_off;
+            roll[n_inst + b] = (long long)I.traj_off;
+            roll[2 * n_inst + b] = (long long)(I.J_off + sizeof(float) * I.S);     // J_1: slab 1 in both layouts
+            roll[3 * n_inst + b] = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? I.N : (I.N & 1)));
+            p->max_slab = std::max(p->max_slab, (long)I.S);
+        }
+    }
     if ((e = hipMemcpy(p->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "table upload");
     return DP_OK;
@@ -964,10 +981,9 @@ static int *queue_slot(dp_plan *p, void *scratch, int slot)
 static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev, hipStream_t s,
                          bool timing = true)
 {
-    for (size_t b = 0; b < p->inst.size(); b++) {
-        const Inst &I = p->inst[b];
-        if (launch_terminal(I.P, slab_ptr(p, I, J, I.N), s)) return hip_fail(hipGetLastError(), "terminal launch");
-    }
+    const int n_inst = (int)p->inst.size();
+    if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, s))
+        return hip_fail(hipGetLastError(), "terminal launch");
     if (launch_fill_i32(queue_slot(p, scratch, 0), 8L * p->n_q_slots, 0, s) ||
         launch_fill_i32((int *)p->dev_count, 2L * (long)p->inst.size(), 0, s))
         return hip_fail(hipGetLastError(), "counter reset launch");
@@ -1045,11 +1061,8 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
         if (R.any_split && launch_combine_jobs(B, R.njobs, R.max_nodes, s))
             return hip_fail(hipGetLastError(), "combine launch");
     }
-    for (size_t b = 0; b < p->inst.size(); b++) {
-        const Inst &I = p->inst[b];
-        if (launch_root(p->dev_insts + b, slab_ptr(p, I, J, 1), V0_dev + b, u0_dev + b, s))
-            return hip_fail(hipGetLastError(), "root launch");
-    }
+    if (launch_root_jobs(p->dev_insts, n_inst, J, p->dev_roll + 2 * n_inst, V0_dev, u0_dev, s))
+        return hip_fail(hipGetLastError(), "root launch");
     return DP_OK;
 }
 
@@ -1260,12 +1273,9 @@ int dp_rollout(dp_plan *p, const void *pi, const int16_t *u0_dev, double *traj_d
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    for (size_t b = 0; b < p->inst.size(); b++) {
-        const Inst &I = p->inst[b];
-        const int16_t *pib = (const int16_t *)((const char *)pi + I.pi_off);
-        if (launch_rollout(I.P, pib, u0_dev + b, traj_dev + I.traj_off, status_dev + 2 * b, s))
-            return hip_fail(hipGetLastError(), "rollout launch");
-    }
+    const int n = (int)p->inst.size();
+    if (launch_rollout_jobs(p->dev_insts, n, pi, p->dev_roll, p->dev_roll + n, u0_dev, traj_dev, status_dev, s))
+        return hip_fail(hipGetLastError(), "rollout launch");
     return DP_OK;
 }
 

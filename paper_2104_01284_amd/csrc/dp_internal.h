@@ -7,14 +7,18 @@
 
 namespace ecodp {
 
-int launch_terminal(const DevInst &P, float *JN, hipStream_t s);
+// Every instance's terminal slab (grid y = instance) and root step in one
+// launch each; per-instance byte offsets of J_N and J_1 from J.
+int launch_terminal_jobs(const DevInst *insts, int n_inst, long max_slab, void *J, const long long *jN_off,
+                         hipStream_t s);
 int launch_terminal_shift(const float *src, long nvs, int n_src, double h_src, double t_shift, int n_dst, double h_dst,
                           double Jinf, float *dst, hipStream_t s);
 int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, unsigned long long *count,
                        hipStream_t s);
 int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *pik, const StageEntry *st,
                  const BatEntry *bat, const TLEntry *tl, hipStream_t s);
-int launch_root(const DevInst *Pdev, const float *J1, float *V0, int16_t *u0, hipStream_t s);
+int launch_root_jobs(const DevInst *insts, int n_inst, const void *J, const long long *j1_off, float *V0, int16_t *u0,
+                     hipStream_t s);
 
 // Grouped sweep geometry: floats per staged plane row (time nodes plus at
 // least one padding column, rounded up to 32 so that the rows of a small grid
@@ -36,8 +40,9 @@ int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int nj
 int launch_combine_jobs(const StageBase &B, int njobs, long max_nodes, hipStream_t s);
 int launch_fill_i32(int *p, long n, int v, hipStream_t s);
 
-int launch_rollout(const DevInst &P, const int16_t *pi, const int16_t *u0, double *traj, int32_t *status,
-                   hipStream_t s);
+// Every instance's rollout in one launch (one wave each); offsets per instance.
+int launch_rollout_jobs(const DevInst *insts, int n_inst, const void *pi, const long long *pi_off,
+                        const long long *traj_off, const int16_t *u0, double *traj, int32_t *status, hipStream_t s);
 int launch_fill_f64(double *p, long n, double v, hipStream_t s);
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
                         double *gstage, hipStream_t s);

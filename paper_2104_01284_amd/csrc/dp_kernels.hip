@@ -10,9 +10,12 @@ namespace ecodp {
 
 // J_N = min(J_inf, w_soc (xi_j - xi_ref)^2 + terminal_V) in FP64, one FP32
 // rounding; nodes above the stage-N speed limit take J_inf.
-__global__ void k_terminal(DevInst P, float *__restrict__ JN)
+__global__ void k_terminal_jobs(const DevInst *__restrict__ insts, char *__restrict__ J,
+                                const long long *__restrict__ jN_off)
 {
 #pragma clang fp contract(off)
+    const DevInst &P = insts[blockIdx.y];
+    float *__restrict__ JN = (float *)(J + jN_off[blockIdx.y]);
     const long S = (long)P.n_v * P.n_s * P.n_t;
     for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
         const int m = (int)(n % P.n_t);
@@ -248,11 +251,9 @@ __global__ void __launch_bounds__(1024) k_sweep_naive(DevInst P, int k, const fl
 // the workgroup.
 // The parameter block comes from device memory, so that a recorded solve
 // picks up a state moved by dp_set_state.
-__global__ void __launch_bounds__(256) k_root(const DevInst *__restrict__ Pd, const float *__restrict__ J1, float *V0,
-                                              int16_t *u0)
+__device__ void root_one(const DevInst &P, const float *__restrict__ J1, float *V0, int16_t *u0)
 {
 #pragma clang fp contract(off)
-    const DevInst &P = *Pd;
     __shared__ float sv[256];
     __shared__ int su[256];
     const float Jinf = (float)P.Jinf;
@@ -317,14 +318,24 @@ __global__ void __launch_bounds__(256) k_root(const DevInst *__restrict__ Pd, co
     }
 }
 
+// Every instance's root step in one launch, one workgroup per instance; J_1
+// of instance b at byte offset j1_off[b] from J.
+__global__ void __launch_bounds__(256) k_root_jobs(const DevInst *__restrict__ insts, const char *__restrict__ J,
+                                                   const long long *__restrict__ j1_off, float *V0, int16_t *u0)
+{
+    const int b = blockIdx.x;
+    root_one(insts[b], (const float *)(J + j1_off[b]), V0 + b, u0 + b);
+}
+
 // ------------------------------------------------------------------ launch --
 
-int launch_terminal(const DevInst &P, float *JN, hipStream_t s)
+int launch_terminal_jobs(const DevInst *insts, int n_inst, long max_slab, void *J, const long long *jN_off,
+                         hipStream_t s)
 {
-    const long S = (long)P.n_v * P.n_s * P.n_t;
-    int blocks = (int)((S + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_terminal, dim3(blocks), dim3(256), 0, s, P, JN);
+    long blocks = (max_slab + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_terminal_jobs, dim3((unsigned)blocks, n_inst), dim3(256), 0, s, insts, (char *)J, jN_off);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -347,9 +358,10 @@ int launch_sweep(const DevInst &P, int k, const float *Jn, float *Jk, int16_t *p
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_root(const DevInst *Pdev, const float *J1, float *V0, int16_t *u0, hipStream_t s)
+int launch_root_jobs(const DevInst *insts, int n_inst, const void *J, const long long *j1_off, float *V0, int16_t *u0,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, Pdev, J1, V0, u0);
+    hipLaunchKernelGGL(k_root_jobs, dim3(n_inst), dim3(256), 0, s, insts, (const char *)J, j1_off, V0, u0);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
