@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--split", type=int, default=0, help="control slices per node tile (0 automatic)")
     ap.add_argument("--wg-per-cu", type=int, default=0, help="resident sweep workgroups per CU (0 automatic)")
     ap.add_argument("--kernel", type=int, default=0, help="sweep variant (0 automatic, 1 simple, 2 grouped)")
+    ap.add_argument("--rounds", action="store_true",
+                    help="batched workload: rounds of launches instead of the persistent sweep")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's own sweep configuration instead of the autotuner's")
     ap.add_argument("--mpc-repeats", type=int, default=20,
@@ -227,7 +229,8 @@ def main():
     insts = instances.batched(256) if batched else [instances.make(args.workload)]
     inst = insts[0]
     print(f"[bench] workload {DESCR[args.workload]}", file=sys.stderr, flush=True)
-    opts = dict(sweep_tile=args.tile, split=args.split, wg_per_cu=args.wg_per_cu, kernel=args.kernel)
+    opts = dict(sweep_tile=args.tile, split=args.split, wg_per_cu=args.wg_per_cu, kernel=args.kernel,
+                rounds=args.rounds)
     tuned = None
     # a batch keeps the library's per-instance choice: the tuner times shapes
     # alone, while in a batch they share the GPU with the other instances
@@ -253,6 +256,7 @@ def main():
         plan = Plan(insts, store_all=True, timing=True, **opts)
     evals = plan.evaluations()
     info = plan.info[0]
+    persistent = bool(info.sweep_persistent)
 
     def step():
         plan.solve()
@@ -363,7 +367,9 @@ def main():
                      "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "state sweep", "avg_launch_ms": avg_launch_ms, "launches_per_solve": launches,
+                     "kernel": ("persistent state sweep (one launch per kernel class, side by side; "
+                                "one interval per solve)" if persistent else "state sweep"),
+                     "avg_launch_ms": avg_launch_ms, "launches_per_solve": launches,
                      "flops_per_launch": FLOPS_PER_EVAL * evals / max(1, launches),
                      "executed_evaluations_per_solve": executed,
                      "executed_over_dense": executed / evals,
@@ -380,6 +386,12 @@ def main():
     from paper_2104_01284_amd.profiling import golden_report, load_golden
     g = None if batched else load_golden(args.workload, inst)
     out["V0_rel_err_vs_oracle"] = None
+    if batched:
+        from paper_2104_01284_amd.profiling import batch_golden_report
+        rep_ = batch_golden_report(insts, plan.V0.cpu().tolist(), plan.u0.cpu().tolist())
+        if rep_ is not None:
+            out["V0_rel_err_vs_oracle"] = rep_["V0_max_rel_err"]
+            out["errors_vs_fp64_oracle"] = rep_
     if g is not None:
         trajs, _ = plan.rollout()
         grad = plan.adjoint()

@@ -71,6 +71,12 @@ enum {
 #define DP_GRAPH 4u            /* dp_solve records its launches once into a HIP graph and replays it;
                                   the graph is recorded again when the buffers change.  Not with
                                   DP_TIMING. */
+#define DP_ROUNDS 8u           /* a plan of several instances solves in rounds of launches (round r:
+                                  stage N_b-1-r of every instance b) instead of the persistent sweep */
+#define DP_STALL_TEST 16u      /* test hook of the persistent sweep's bounded wait: the first job of
+                                  every queue waits for a count that is never reached, gives up after
+                                  1000 polls and sets the device error word (dp_device_check reports
+                                  DP_EDEVICE); the solve's results are then not valid */
 
 /* One receding-horizon problem (Eq. 6-8).  Host pointers; copied at build. */
 typedef struct {
@@ -127,6 +133,8 @@ typedef struct {
     int32_t sweep_split;       /* control slices per node tile (grouped sweep)                     */
     int32_t sweep_grid;        /* persistent workgroups of one grouped-sweep launch                */
     int32_t soc_shift;         /* host bound H on the SoC-cell shift of one step                   */
+    int32_t sweep_persistent;  /* 1: solved by the plan's persistent multi-instance sweep (then
+                                  sweep_split is 1 and sweep_grid the workgroups of its kernel class) */
 } dp_instance_info;
 
 /* Validate n_inst problem descriptions, precompute host-side tables in FP64
@@ -147,9 +155,14 @@ int dp_instance_info_get(const dp_plan *p, int32_t inst, dp_instance_info *info)
  * k = N-1..0 the stage table and the state sweep (min and argmin over all
  * controls at every node), then the exact first step at x0 (Eq. 6):
  * V0_dev[inst] = min(J_inf, min_u c + interp J_1), u0_dev[inst] = argmin or -1.
- * All instances run in rounds of one stage each (round r: stage N_b-1-r of
- * every instance b with N_b > r); each instance's results are bit for bit
- * those of a plan holding it alone.  Among exactly equal candidates the
+ * A plan of several instances on the grouped sweep runs one persistent launch
+ * per kernel class (SoC tile and workgroup size): each instance is served by
+ * the workgroups of one XCD, whose stage-k work waits (bounded) on a device
+ * counter of the instance's finished stage-(k+1) work; a wait that gives up
+ * sets the device error word (dp_device_check).  With DP_ROUNDS, or when the
+ * persistent sweep does not fit, the instances run in rounds of one stage each
+ * (round r: stage N_b-1-r of every instance b with N_b > r).  Either way each
+ * instance's results are bit for bit those of a plan holding it alone.  Among exactly equal candidates the
  * grouped sweep keeps the first in its visit order (successor speed cell,
  * then control index); the simple sweep keeps the lowest control index.
  * With DP_GRAPH the launches are recorded into a HIP graph on the first call

@@ -18,6 +18,8 @@ DP_TERMINAL_DEVICE = 2
 DP_STORE_ALL_V = 1
 DP_TIMING = 2
 DP_GRAPH = 4
+DP_ROUNDS = 8
+DP_STALL_TEST = 16
 
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_solve_static",
            "dp_stage", "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_adjoint_grade",
@@ -54,7 +56,7 @@ class DpInstanceInfo(C.Structure):
                 ("n_u", C.c_int32), ("J_offset", C.c_size_t), ("pi_offset", C.c_size_t),
                 ("traj_offset", C.c_size_t), ("slab_elems", C.c_size_t), ("evaluations", C.c_int64),
                 ("sweep_kernel", C.c_int32), ("sweep_tile", C.c_int32), ("sweep_split", C.c_int32),
-                ("sweep_grid", C.c_int32), ("soc_shift", C.c_int32)]
+                ("sweep_grid", C.c_int32), ("soc_shift", C.c_int32), ("sweep_persistent", C.c_int32)]
 
 
 _lib = None

@@ -98,14 +98,17 @@ class Plan:
 
     ``Plan(instances, store_all=False, timing=False, device=0)`` validates the
     instances and uploads their parameter blocks; ``solve()`` runs the backward
-    recursion of every instance on the current torch stream, all instances in
-    rounds of one stage each.  ``graph=True`` records the solve once into a HIP
-    graph and replays it on later calls.
+    recursion of every instance on the current torch stream, several instances
+    in one persistent sweep (or, with ``rounds=True``, in rounds of one stage
+    each).
+    ``graph=True`` records the solve once into a HIP graph and replays it on
+    later calls; ``stall_test=True`` sets the persistent sweep's test hook
+    (its bounded wait gives up and raises the device error word).
     """
 
     def __init__(self, instances, store_all: bool = False, timing: bool = False, device: int = 0,
                  sweep_tile: int = 0, kernel: int = 0, split: int = 0, wg_per_cu: int = 0,
-                 graph: bool = False, inst_opts=None):
+                 graph: bool = False, inst_opts=None, rounds: bool = False, stall_test: bool = False):
         import torch
         self.torch = torch
         if isinstance(instances, dict):
@@ -116,7 +119,7 @@ class Plan:
         arr = (L.DpProblemDesc * len(self._descs))(*[x.d for x in self._descs])
         opt = L.DpOptions()
         opt.flags = (L.DP_STORE_ALL_V if store_all else 0) | (L.DP_TIMING if timing else 0) | \
-            (L.DP_GRAPH if graph else 0)
+            (L.DP_GRAPH if graph else 0) | (L.DP_ROUNDS if rounds else 0) | (L.DP_STALL_TEST if stall_test else 0)
         opt.tile[0] = int(sweep_tile)
         opt.tile[1] = int(split)
         opt.tile[2] = int(wg_per_cu)

@@ -414,26 +414,88 @@ __global__ void __launch_bounds__(256) k_adj_reduce(const double *__restrict__ g
                                                red[3][threadIdx.x];
 }
 
+// The FP64 step terms of one stage that depend on the speed node and the
+// control only (Eq. 5a, 2, 1 and their theta partials, as step_partials): a
+// table over (i, u), so that an occupied node only adds the battery and SoC
+// terms.  ok = 0 for a pair the stage does not admit (the node's successor
+// is then not formed).
+struct AdjEntry {
+    double dt, Pb, fv, ft;
+    double dc[3];        // d cost / d(M, CdA, Crr)
+    double drv[3];       // d r_v / d(M, CdA, Crr)
+    double ddt[3];       // d dt / d(M, CdA, Crr)
+    double drt[3];       // d r_t / d(M, CdA, Crr)
+    int cv, dtc, ok, pad;
+};
+
+__global__ void __launch_bounds__(256) k_adj_table(DevInst P, int k, AdjEntry *__restrict__ tab)
+{
+#pragma clang fp contract(off)
+    const long n = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (n >= (long)P.n_v * P.n_u) return;
+    const int i = (int)(n / P.n_u), u = (int)(n % P.n_u);
+    const double v = P.v_lo + i * P.hv;
+    const PT p = powertrain(P, k, v, u / P.n_m, u % P.n_m);
+    AdjEntry e;
+    e.ok = 0;
+    e.dt = p.dt;
+    e.Pb = p.Pb;
+    e.cv = 0;
+    e.fv = 0.0;
+    e.dtc = 0;
+    e.ft = 0.0;
+    const double rv = (p.v1 - P.v_lo) / P.hv;
+    const double delta = p.dt / P.ht;
+    if (p.st == 0 && rv >= 0.0 && rv <= P.n_v - 1 && delta < P.n_t) {
+        e.ok = 1;
+        cell_of(rv, P.n_v, e.cv, e.fv);
+        const double fl = floor(delta);
+        e.dtc = (int)fl;
+        e.ft = delta - fl;
+    }
+    // the partials of step_partials for theta = M, CdA, Crr (w_t enters the
+    // cost as dt, w_soc only the terminal cost)
+    double dq[3];
+    dq[0] = 2.0 * P.ds * (-P.g * (P.Crr * p.cosa + p.sina) / P.M - (p.Ftr - p.Froad) / (P.M * P.M));
+    dq[1] = -P.ds * P.rho * v * v / P.M;
+    dq[2] = -2.0 * P.ds * P.g * p.cosa;
+    for (int q = 0; q < 3; q++) {
+        const double dv1 = p.q > 0.0 ? dq[q] / (2.0 * p.v1) : 0.0;
+        const double vs = v + p.v1;
+        const double ddt = -2.0 * P.ds / (vs * vs) * dv1;
+        e.dc[q] = (p.mf + P.wt) * ddt;
+        e.drv[q] = dv1 / P.hv;
+        e.ddt[q] = ddt;
+        e.drt[q] = ddt / P.ht;
+    }
+    e.pad = 0;
+    tab[n] = e;
+}
+
 // Stage k >= 1: every node with occupancy rho > 0 follows its stored control:
 // gradient terms weighted by rho, and rho times the interpolation weights
 // added to the stage k+1 occupancy.  Wait nodes add rho * tau to dV/dw_t and
 // move in time only.  Nodes without a control keep J_inf and stop the mass.
 // Each workgroup takes a chunk of kAdjChunk consecutive nodes, gathers the
-// ones with rho > 0 into an LDS list (the occupied set is a small part of the
-// grid) and then runs the FP64 work on full waves.
-constexpr int kAdjChunk = 512;
+// ones with rho > 0 (and their rho) into LDS lists, zeroing them in rho (so
+// that the buffer is all zero again when it becomes the occupancy two stages
+// later), and then runs the FP64 work on full waves: per node the (i, u)
+// entry of the stage table, the battery current and SoC cell (Eq. 5b), the
+// interpolation gradient and the scatter.
+constexpr int kAdjChunk = 1024;
 
 // SPAT: also the signal-timing sums of the wait nodes (a separate instance, so
 // that the plain adjoint keeps its registers).
 template <bool SPAT>
-__global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float *__restrict__ Jn,
-                                                   const int16_t *__restrict__ pik, const TLEntry *__restrict__ tl,
-                                                   const double *__restrict__ rho, double *__restrict__ rho_next,
-                                                   double *__restrict__ gacc, double *__restrict__ gcrr,
-                                                   double *__restrict__ gspat)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__restrict__ pik,
+            const TLEntry *__restrict__ tl, const AdjEntry *__restrict__ tab, double *__restrict__ rho,
+            double *__restrict__ rho_next, double *__restrict__ gacc, double *__restrict__ gcrr,
+            double *__restrict__ gspat)
 {
 #pragma clang fp contract(off)
     __shared__ int s_list[kAdjChunk];
+    __shared__ double s_rho[kAdjChunk];
     __shared__ int s_cnt;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double sO = 0.0, sC = 0.0;   // signal timing: sum of rho dval/dtau, and of rho n dval/dtau
@@ -444,18 +506,24 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
         __syncthreads();
         for (int j = threadIdx.x; j < kAdjChunk; j += blockDim.x) {
             const long n = c0 + j;
-            const bool act = n < S && rho[n] > 0.0;
+            const double r = n < S ? rho[n] : 0.0;
+            const bool act = r > 0.0;
             const unsigned long long msk = __ballot(act);
             int off = 0;
             if (lane == 0 && msk) off = atomicAdd(&s_cnt, __popcll(msk));
             off = __shfl(off, 0);
-            if (act) s_list[off + __popcll(msk & ((1ull << lane) - 1ull))] = j;
+            if (act) {
+                const int slot = off + __popcll(msk & ((1ull << lane) - 1ull));
+                s_list[slot] = j;
+                s_rho[slot] = r;
+                rho[n] = 0.0;
+            }
         }
         __syncthreads();
         const int na = s_cnt;
         for (int a = threadIdx.x; a < na; a += blockDim.x) {
             const long n = c0 + s_list[a];
-            const double r = rho[n];
+            const double r = s_rho[a];
             const int m = (int)(n % P.n_t);
             const long ij = n / P.n_t;
             const int j = (int)(ij % P.n_s);
@@ -479,17 +547,34 @@ __global__ void __launch_bounds__(256) k_adj_stage(DevInst P, int k, const float
                 if (1.0 - e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc], r * (1.0 - e.wf));
                 if (e.wf > 0.0) unsafeAtomicAdd(&rho_next[base + e.wc + 1], r * e.wf);
             } else if (u >= 0) {
-                PT p;
-                double I;
-                Cells x;
-                const double v = P.v_lo + i * P.hv;
+                // the successor exactly as successor_cells forms it, the
+                // (i, u) terms from the stage table
+                const AdjEntry &e = tab[(long)i * P.n_u + u];
+                if (!e.ok) continue;
                 const double xi = P.s_lo + j * P.hs;
-                if (!successor_cells(P, k, v, xi, (double)j, m, u, p, I, x)) continue;
-                double dc[5], dr[5][3], gJ[3];
-                step_partials(P, v, p, I, dc, dr);
+                double I;
+                if (!battery_current(P, e.Pb, xi, I)) continue;
+                const double rs = (double)j - (e.dt * I) / (P.Cnom * P.hs);
+                if (!(rs >= 0.0 && rs <= P.n_s - 1)) continue;
+                Cells x;
+                x.c[0] = e.cv;
+                x.f[0] = e.fv;
+                cell_of(rs, P.n_s, x.c[1], x.f[1]);
+                int tc = m + e.dtc;
+                double ft = e.ft;
+                if (tc > P.n_t - 2) {
+                    ft += (double)(tc - (P.n_t - 2));
+                    tc = P.n_t - 2;
+                    if (ft > 1.0) continue;
+                }
+                x.c[2] = tc;
+                x.f[2] = ft;
+                double gJ[3];
                 interp_grad(P, Jn, x, gJ);
-                for (int q = 0; q < 5; q++)
-                    g[q] += r * (dc[q] + dr[q][0] * gJ[0] + dr[q][1] * gJ[1] + dr[q][2] * gJ[2]);
+                const double sI = -(I / (P.Cnom * P.hs));
+                for (int q = 0; q < 3; q++)
+                    g[q] += r * (e.dc[q] + e.drv[q] * gJ[0] + (sI * e.ddt[q]) * gJ[1] + e.drt[q] * gJ[2]);
+                g[3] += r * e.dt;
                 scatter(P, rho_next, r, x, true);
             }
         }
@@ -558,18 +643,28 @@ int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, do
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+size_t adjoint_table_bytes(const DevInst &P) { return sizeof(AdjEntry) * (size_t)P.n_v * P.n_u; }
+
+int launch_adjoint_table(const DevInst &P, int k, void *tab, hipStream_t s)
+{
+    const long n = (long)P.n_v * P.n_u;
+    hipLaunchKernelGGL(k_adj_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, k, (AdjEntry *)tab);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
-                         const double *rho, double *rho_next, double *gacc, double *gstage, double *gspat_L,
-                         hipStream_t s)
+                         const void *tab, double *rho, double *rho_next, double *gacc, double *gstage,
+                         double *gspat_L, hipStream_t s)
 {
     // kAdjBlocks workgroups walk the chunks, each adding into its own slot
     // (and, at a signal, storing its pair of gspat_L)
     double *gcrr = gstage ? gstage + (long)k * kAdjBlocks : nullptr;
+    const AdjEntry *t = (const AdjEntry *)tab;
     if (tl && gspat_L)
-        hipLaunchKernelGGL(k_adj_stage<true>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next,
+        hipLaunchKernelGGL(k_adj_stage<true>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, t, rho, rho_next,
                            gacc, gcrr, gspat_L);
     else
-        hipLaunchKernelGGL(k_adj_stage<false>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, rho, rho_next,
+        hipLaunchKernelGGL(k_adj_stage<false>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, t, rho, rho_next,
                            gacc, gcrr, nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

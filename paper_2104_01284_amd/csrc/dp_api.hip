@@ -110,6 +110,30 @@ struct dp_plan {
                                      // J_1 and J_N byte offsets
     long max_slab = 0;               // largest slab of any instance
     std::vector<Round> rounds;
+    // persistent batched sweep (several instances, DP_ROUNDS unset): one
+    // launch per kernel class over every stage, tables of every distinct
+    // stage built before it
+    struct PClass {
+        int jt = 0, pitch = 0, threads = 0, grid = 0;
+        size_t lds = 0;
+        int xjb_off = 0;             // ints into dev_pint: job bounds [n_xcd + 1], item totals [n_xcd]
+        int claim_off = 0;           // ints from scr_pc: claim counters [n_xcd]
+        double work = 0.0;
+        std::vector<int> members;
+    };
+    bool persist = false;
+    int n_xcd = 8;
+    std::vector<PClass> pclasses;
+    void *dev_ptables = nullptr;     // PJob queues, their bounds and the table-build jobs
+    PJob *dev_pjobs = nullptr;
+    int *dev_pint = nullptr;
+    StageJob *dev_pbjobs = nullptr;
+    int n_pbjobs = 0, pb_max_nv = 0;
+    long pb_max_records = 0;
+    size_t scr_pc = 0;               // persistent counters: claims of every class, then done per instance
+    long n_pc = 0;
+    int done_off = 0;
+    long long spin_limit = 1LL << 22;   // polls of a persistent wait (each a load and a short sleep): seconds
     void *dev_tables = nullptr;
     DevInst *dev_insts = nullptr;
     StageJob *dev_jobs = nullptr;
@@ -120,6 +144,7 @@ struct dp_plan {
     size_t scr_gpart = 0;            // adjoint partial gradient sums
     size_t scr_gstage = 0;           // adjoint per-stage C_rr shares (grade sensitivities)
     size_t scr_gspat = 0;            // adjoint per-signal wait sums (signal-timing sensitivities)
+    size_t scr_adjtab = 0;           // adjoint per-(speed node, control) table of one stage
     int n_q_slots = 0;
     // independent sweep launches of a round run on these streams side by side
     static constexpr int kSide = 3;
@@ -483,6 +508,10 @@ static int plan_rounds(dp_plan *p, size_t scr)
     for (const Inst &I : p->inst) max_L = std::max(max_L, I.n_lights);
     p->scr_gspat = scr;   // adjoint: per-(signal, workgroup) pairs for the signal-timing sensitivities
     scr += align_up(sizeof(double) * 2 * adjoint_grade_slots() * (size_t)max_L, 256);
+    size_t max_tab = 0;
+    for (const Inst &I : p->inst) max_tab = std::max(max_tab, adjoint_table_bytes(I.P));
+    p->scr_adjtab = scr;  // adjoint: the stage table of the instance being differentiated
+    scr += align_up(max_tab, 256);
     p->bytes_scratch = scr;
 
     const size_t b_inst = align_up(sizeof(DevInst) * n_inst, 256);
@@ -526,12 +555,255 @@ static int plan_rounds(dp_plan *p, size_t scr)
     return DP_OK;
 }
 
+// Persistent batched sweep.  Each instance's stages get their tables from
+// one table set per run of stages with equal tables (built together before
+// the sweep); instances are grouped into kernel classes (SoC tile and waves
+// per workgroup, the LDS pitch of the class's widest time grid) and, within
+// a class, dealt to the XCDs by decreasing work; each XCD queue lists its
+// instances' stage jobs round by round (stage N_b - 1 - r in round r),
+// larger items first inside a round.  No control slices: the instances of a
+// batch already give every CU work.  Falls back to rounds (returns DP_OK
+// with persist unset) when an instance is on the simple sweep or the extra
+// table sets would take more than half of the free device memory.
+// Workgroups of a persistent class per those it needs resident (measured on
+// 256 heterogeneous solves: 1.0 -> 1924 ms, 1.5 -> 1607 ms, 2.5 -> 1513 ms).
+constexpr double kPersistOversub = 2.5;
+
+static int plan_persist(dp_plan *p)
+{
+    const int n_inst = (int)p->inst.size();
+    for (const Inst &I : p->inst)
+        if (I.sweep != 2) return DP_OK;
+    p->n_xcd = std::max(1, p->n_cu / 32);
+    // table sets: per instance, one per run of stages with equal tables
+    std::vector<std::vector<int>> set_of(n_inst);
+    std::vector<std::vector<int>> set_k(n_inst);          // first (highest) stage of each set
+    size_t extra = 0;
+    for (int b = 0; b < n_inst; b++) {
+        const Inst &I = p->inst[b];
+        set_of[b].assign(I.N, 0);
+        int sidx = 0;
+        set_k[b].push_back(I.N - 1);
+        for (int k = I.N - 2; k >= 0; k--) {
+            if (!I.same_tables[k]) {
+                sidx++;
+                set_k[b].push_back(k);
+            }
+            set_of[b][k] = sidx;
+        }
+        if (sidx + 1 > 2) extra += (size_t)(sidx + 1 - 2) * I.tab_stride;
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return DP_OK;
+    }
+    if (extra > free_b / 2) return DP_OK;
+    size_t scr = align_up(p->bytes_scratch, 256);
+    std::vector<size_t> xset(n_inst, 0);
+    for (int b = 0; b < n_inst; b++) {
+        const Inst &I = p->inst[b];
+        const int ns = (int)set_k[b].size();
+        if (ns > 2) {
+            xset[b] = scr;
+            scr += (size_t)(ns - 2) * I.tab_stride;
+            scr = align_up(scr, 256);
+        }
+    }
+    auto set_base = [&](int b, int sidx) -> long long {
+        const Inst &I = p->inst[b];
+        return sidx < 2 ? (long long)(sidx * I.tab_stride) : (long long)(xset[b] + (sidx - 2) * I.tab_stride - I.scr_st);
+    };
+    auto stage_job = [&](int b, int k) {
+        const Inst &I = p->inst[b];
+        StageJob j;
+        std::memset(&j, 0, sizeof j);
+        j.inst = b;
+        j.k = k;
+        j.jt = I.jt;
+        j.ntiles = (I.P.n_s + I.jt - 1) / I.jt;
+        j.nsplit = 1;
+        j.H = I.H;
+        j.rw = sweep_rows(I.jt, I.H);
+        j.nitems = I.P.n_v * j.ntiles;
+        const int L = I.light_of_stage[k];
+        j.tl = L >= 0 ? (int)(I.tl_dev_off + (size_t)L * I.P.n_t) : -1;
+        const bool all = (p->flags & DP_STORE_ALL_V) != 0;
+        j.jn = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k + 1 : ((k + 1) & 1)));
+        j.jk = (long long)(I.J_off + sizeof(float) * I.S * (size_t)(all ? k : (k & 1)));
+        j.pik = (long long)(I.pi_off + sizeof(int16_t) * I.S * (size_t)k);
+        const long long sb = set_base(b, set_of[b][k]);
+        j.st = (long long)I.scr_st + sb;
+        j.nf = (long long)I.scr_nf + sb;
+        j.rec = (long long)I.scr_rec + sb;
+        j.pw = (long long)I.scr_pw + sb;
+        j.pv = j.pu = 0;
+        return j;
+    };
+    // table builds: one job per set
+    std::vector<StageJob> pb;
+    for (int b = 0; b < n_inst; b++) {
+        const Inst &I = p->inst[b];
+        for (int k : set_k[b]) {
+            pb.push_back(stage_job(b, k));
+            p->pb_max_nv = std::max(p->pb_max_nv, I.P.n_v);
+            p->pb_max_records = std::max(p->pb_max_records, (long)I.P.n_v * I.P.n_u * pb.back().ntiles * I.jt);
+        }
+    }
+    p->n_pbjobs = (int)pb.size();
+    // classes by (tile, block)
+    std::vector<int> cls_of(n_inst, -1);
+    for (int b = 0; b < n_inst; b++) {
+        const Inst &I = p->inst[b];
+        const int threads = sweep_threads(I.jt, I.P.n_t);
+        int c = -1;
+        for (size_t q = 0; q < p->pclasses.size(); q++)
+            if (p->pclasses[q].jt == I.jt && p->pclasses[q].threads == threads) c = (int)q;
+        if (c < 0) {
+            dp_plan::PClass C;
+            C.jt = I.jt;
+            C.threads = threads;
+            p->pclasses.push_back(C);
+            c = (int)p->pclasses.size() - 1;
+        }
+        cls_of[b] = c;
+        dp_plan::PClass &C = p->pclasses[c];
+        C.members.push_back(b);
+        C.pitch = std::max(C.pitch, sweep_pitch(I.P.n_t));
+    }
+    for (dp_plan::PClass &C : p->pclasses) {
+        if (C.pitch > 512 || C.threads > 1024) {
+            p->pclasses.clear();
+            return DP_OK;
+        }
+        for (int b : C.members) C.lds = std::max(C.lds, lds_sweep_bytes_p(C.jt, p->inst[b].H, C.pitch, C.threads));
+        if (C.lds > (size_t)p->lds_per_cu) {
+            p->pclasses.clear();
+            return DP_OK;
+        }
+    }
+    // Instances to XCDs, the longest first onto the least-loaded XCD, over
+    // all classes together (a class's workgroups are spread evenly over the
+    // XCDs, its instances are not).  Work is counted in wave time: node-control
+    // evaluations over the time nodes, times the waves of a workgroup (a wave
+    // covers 63 time nodes, however few of them are on the grid).
+    std::vector<double> wt(n_inst);
+    for (int b = 0; b < n_inst; b++) {
+        const Inst &I = p->inst[b];
+        wt[b] = (double)I.evals * (double)(sweep_threads(I.jt, I.P.n_t) / 64) / (double)I.P.n_t;
+    }
+    std::vector<int> order(n_inst);
+    for (int b = 0; b < n_inst; b++) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return wt[a] > wt[b]; });
+    std::vector<int> xcd_of(n_inst, 0);
+    std::vector<double> load(p->n_xcd, 0.0);
+    for (int b : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        xcd_of[b] = x;
+        load[x] += wt[b];
+    }
+    // queues
+    std::vector<PJob> pj;
+    std::vector<int> pint;
+    int claim = 0;
+    const int cu_per_xcd = std::max(1, p->n_cu / p->n_xcd);
+    for (int c = 0; c < (int)p->pclasses.size(); c++) {
+        dp_plan::PClass &C = p->pclasses[c];
+        std::vector<std::vector<int>> xq(p->n_xcd);
+        std::vector<double> wx(p->n_xcd, 0.0);
+        for (int b : order)
+            if (cls_of[b] == c) {
+                xq[xcd_of[b]].push_back(b);
+                wx[xcd_of[b]] += wt[b];
+                C.work += wt[b];
+            }
+        C.xjb_off = (int)pint.size();
+        std::vector<int> bounds, totals;
+        int max_total = 1;
+        for (int x = 0; x < p->n_xcd; x++) {
+            bounds.push_back((int)pj.size());
+            int maxN = 0;
+            for (int b : xq[x]) maxN = std::max(maxN, p->inst[b].N);
+            int item0 = 0;
+            for (int r = 0; r < maxN; r++) {
+                std::vector<int> rb;
+                for (int b : xq[x])
+                    if (p->inst[b].N > r) rb.push_back(b);
+                std::stable_sort(rb.begin(), rb.end(), [&](int a, int b) {
+                    return (double)p->inst[a].P.n_u * p->inst[a].P.n_t > (double)p->inst[b].P.n_u * p->inst[b].P.n_t;
+                });
+                for (int b : rb) {
+                    PJob e;
+                    std::memset(&e, 0, sizeof e);
+                    e.j = stage_job(b, p->inst[b].N - 1 - r);
+                    e.need = r * e.j.nitems;
+                    e.item0 = item0;
+                    item0 += e.j.nitems;
+                    pj.push_back(e);
+                }
+            }
+            totals.push_back(item0);
+            max_total = std::max(max_total, item0);
+        }
+        bounds.push_back((int)pj.size());
+        pint.insert(pint.end(), bounds.begin(), bounds.end());
+        pint.insert(pint.end(), totals.begin(), totals.end());
+        C.claim_off = claim;
+        claim += p->n_xcd;
+        // workgroups per XCD: the class's share of the work of an XCD times
+        // the workgroups of the class an XCD holds, for the XCD that needs
+        // the most (the classes run side by side; elsewhere the surplus
+        // workgroups find their queue drained and leave), times
+        // kPersistOversub: workgroups beyond the resident ones start as
+        // those of classes that finish early leave, so the last classes
+        // still fill the chip
+        int per_cu = persist_blocks_per_cu(C.jt, C.pitch, C.threads, C.lds);
+        if (per_cu < 1) {
+            per_cu = (int)std::max<size_t>(1, (size_t)p->lds_per_cu / C.lds);
+            per_cu = std::max(1, std::min(per_cu, 32 / std::max(1, C.threads / 64)));
+        }
+        long per_x = 1;
+        for (int x = 0; x < p->n_xcd; x++)
+            if (wx[x] > 0.0 && load[x] > 0.0)
+                per_x = std::max<long>(per_x, (long)std::ceil(kPersistOversub * wx[x] / load[x] * per_cu * cu_per_xcd));
+        per_x = std::min<long>(per_x, max_total);
+        C.grid = (int)(per_x * p->n_xcd);
+    }
+    // device tables
+    const size_t b_pj = align_up(sizeof(PJob) * std::max<size_t>(1, pj.size()), 256);
+    const size_t b_pi = align_up(sizeof(int) * std::max<size_t>(1, pint.size()), 256);
+    const size_t b_pb = align_up(sizeof(StageJob) * std::max<size_t>(1, pb.size()), 256);
+    hipError_t e = hipMalloc(&p->dev_ptables, b_pj + b_pi + b_pb);
+    if (e != hipSuccess) return fail(DP_ENOMEM, "hipMalloc of %zu persistent-table bytes: %s", b_pj + b_pi + b_pb,
+                                     hipGetErrorString(e));
+    std::vector<unsigned char> host(b_pj + b_pi + b_pb, 0);
+    if (!pj.empty()) std::memcpy(host.data(), pj.data(), sizeof(PJob) * pj.size());
+    if (!pint.empty()) std::memcpy(host.data() + b_pj, pint.data(), sizeof(int) * pint.size());
+    if (!pb.empty()) std::memcpy(host.data() + b_pj + b_pi, pb.data(), sizeof(StageJob) * pb.size());
+    char *d = (char *)p->dev_ptables;
+    p->dev_pjobs = (PJob *)d;
+    p->dev_pint = (int *)(d + b_pj);
+    p->dev_pbjobs = (StageJob *)(d + b_pj + b_pi);
+    if ((e = hipMemcpy(p->dev_ptables, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "persistent table upload");
+    // counters: claims of every class, then done per instance
+    p->scr_pc = scr;
+    p->done_off = claim;
+    p->n_pc = (long)claim + n_inst;
+    scr += align_up(sizeof(int) * (size_t)p->n_pc, 256);
+    p->bytes_scratch = scr;
+    if (p->flags & DP_STALL_TEST) p->spin_limit = 1000;
+    p->persist = true;
+    return DP_OK;
+}
+
 int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_options *opt, int device, dp_plan **out)
 {
     if (!out) return fail(DP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!desc || n_inst < 1) return fail(DP_EINVAL, "need at least one problem description");
-    if (opt && (opt->flags & ~(DP_STORE_ALL_V | DP_TIMING | DP_GRAPH))) return fail(DP_EINVAL, "unknown option flags");
+    if (opt && (opt->flags & ~(DP_STORE_ALL_V | DP_TIMING | DP_GRAPH | DP_ROUNDS | DP_STALL_TEST)))
+        return fail(DP_EINVAL, "unknown option flags");
     if (opt && (opt->flags & DP_GRAPH) && (opt->flags & DP_TIMING))
         return fail(DP_EINVAL, "option flags DP_GRAPH and DP_TIMING exclude each other");
     if (n_inst > 1024) return fail(DP_EUNSUPPORTED, "at most 1024 instances per plan");
@@ -735,12 +1007,13 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         I.H = soc_shift_bound(P, d);
         // SoC rows per workgroup: 8-row tiles when they leave five resident
         // waves per SIMD (the sweep waits on LDS and barriers, so resident
-        // waves matter more than the per-tile saving), six in a batch, where
-        // the launches of a round share the CUs; else 16 rows on two wave
-        // groups (single instances only), then 4, by the same bound; else
-        // the tile with the most resident waves; a caller tile (or the
+        // waves matter more than the per-tile saving), in a batch too (256
+        // heterogeneous solves: 8-row tiles 1266 ms persistent, 1370 ms in
+        // rounds, against 1527 / 1465 ms with 4-row tiles); else 16 rows on
+        // two wave groups (single instances only), then 4, by the same bound;
+        // else the tile with the most resident waves; a caller tile (or the
         // autotuner) overrides
-        const double min_waves = n_inst > 1 ? 6.0 : 5.0;
+        const double min_waves = 5.0;
         const size_t lds_cu = (size_t)p->lds_per_cu;
         // resident waves per SIMD of the grouped sweep with tile t: bounded by
         // the LDS of a CU, by 8 waves per SIMD and by the kernel's registers
@@ -844,6 +1117,13 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         dp_destroy(p);
         return rc;
     }
+    if (n_inst > 1 && !(p->flags & DP_ROUNDS)) {
+        rc = plan_persist(p);
+        if (rc) {
+            dp_destroy(p);
+            return rc;
+        }
+    }
     if (p->flags & DP_GRAPH) {
         if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
             dp_destroy(p);
@@ -859,7 +1139,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             return hip_fail(e, "table stream");
         }
     }
-    bool multi = false;
+    bool multi = p->persist && p->pclasses.size() > 1;
     for (const Round &R : p->rounds) multi = multi || R.sweeps.size() > 1;
     if (multi) {
         e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
@@ -905,6 +1185,15 @@ int dp_instance_info_get(const dp_plan *p, int32_t inst, dp_instance_info *info)
     info->sweep_split = I.nsplit;
     info->sweep_grid = I.grid;
     info->soc_shift = I.H;
+    info->sweep_persistent = 0;
+    if (p->persist)
+        for (const dp_plan::PClass &C : p->pclasses)
+            for (int b : C.members)
+                if (b == inst) {
+                    info->sweep_persistent = 1;
+                    info->sweep_split = 1;
+                    info->sweep_grid = C.grid;
+                }
     return DP_OK;
 }
 
@@ -978,9 +1267,13 @@ static int *queue_slot(dp_plan *p, void *scratch, int slot)
 
 // The terminal slabs, every round of stages, then the exact root step.
 // timing = false leaves the DP_TIMING events out (they are created on demand).
+static int enqueue_persist(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev,
+                           hipStream_t s, bool timing);
+
 static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev, hipStream_t s,
                          bool timing = true)
 {
+    if (p->persist) return enqueue_persist(p, J, pi, scratch, V0_dev, u0_dev, s, timing);
     const int n_inst = (int)p->inst.size();
     if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, s))
         return hip_fail(hipGetLastError(), "terminal launch");
@@ -1061,6 +1354,68 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
         if (R.any_split && launch_combine_jobs(B, R.njobs, R.max_nodes, s))
             return hip_fail(hipGetLastError(), "combine launch");
     }
+    if (launch_root_jobs(p->dev_insts, n_inst, J, p->dev_roll + 2 * n_inst, V0_dev, u0_dev, s))
+        return hip_fail(hipGetLastError(), "root launch");
+    return DP_OK;
+}
+
+// The persistent solve: counters cleared, terminal slabs, every table set,
+// one persistent sweep per class (side by side), roots.
+static int enqueue_persist(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_t *u0_dev,
+                           hipStream_t s, bool timing)
+{
+    const int n_inst = (int)p->inst.size();
+    int *pc = (int *)((char *)scratch + p->scr_pc);
+    if (launch_fill_i32(pc, p->n_pc, 0, s) || launch_fill_i32((int *)p->dev_count, 2L * n_inst, 0, s))
+        return hip_fail(hipGetLastError(), "counter reset launch");
+    if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, s))
+        return hip_fail(hipGetLastError(), "terminal launch");
+    const StageBase base = stage_base(p, J, pi, scratch);
+    {
+        StageBase Bt = base;
+        Bt.jobs = p->dev_pbjobs;
+        if (launch_stage_jobs(Bt, p->n_pbjobs, p->pb_max_nv, p->pb_max_records, s))
+            return hip_fail(hipGetLastError(), "stage table launch");
+    }
+    // with DP_TIMING the classes still run side by side: one interval from
+    // before the fork to after the join
+    const bool timed = timing && (p->flags & DP_TIMING);
+    const int ncls = (int)p->pclasses.size();
+    const int nside = std::min<int>(dp_plan::kSide, ncls - 1);
+    if (timed) {
+        int rc = time_begin(p, s);
+        if (rc) return rc;
+    }
+    if (nside > 0) {
+        hipError_t e = hipEventRecord(p->fork, s);
+        for (int q = 0; q < nside && e == hipSuccess; q++) e = hipStreamWaitEvent(p->side[q], p->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "stream fork");
+    }
+    for (int c = 0; c < ncls; c++) {
+        const dp_plan::PClass &C = p->pclasses[c];
+        hipStream_t ls = (nside > 0 && c % (nside + 1) != 0) ? p->side[c % (nside + 1) - 1] : s;
+        PersistQueues Q;
+        Q.jobs = p->dev_pjobs;
+        Q.xjb = p->dev_pint + C.xjb_off;
+        Q.xtot = p->dev_pint + C.xjb_off + p->n_xcd + 1;
+        Q.claim = pc + C.claim_off;
+        Q.done = pc + p->done_off;
+        Q.err = p->dev_err;
+        Q.n_xcd = p->n_xcd;
+        Q.stall = (p->flags & DP_STALL_TEST) ? 1 : 0;
+        Q.spin_limit = p->spin_limit;
+        if (launch_sweep_persist(C.jt, C.pitch, C.threads, base, p->dev_insts, Q, C.grid, C.lds, ls))
+            return hip_fail(hipGetLastError(), "persistent sweep launch");
+    }
+    if (nside > 0) {
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < nside && e == hipSuccess; q++) {
+            e = hipEventRecord(p->join[q], p->side[q]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join[q], 0);
+        }
+        if (e != hipSuccess) return hip_fail(e, "stream join");
+    }
+    if (timed) time_end(p, s);
     if (launch_root_jobs(p->dev_insts, n_inst, J, p->dev_roll + 2 * n_inst, V0_dev, u0_dev, s))
         return hip_fail(hipGetLastError(), "root launch");
     return DP_OK;
@@ -1300,7 +1655,8 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
         const float *Jb = (const float *)((const char *)J + I.J_off);
         const int16_t *pib = (const int16_t *)((const char *)pi + I.pi_off);
         double *gpart = (double *)((char *)scratch + p->scr_gpart);
-        if (launch_fill_f64(g, 5, 0.0, s) || launch_fill_f64(rho_a, (long)I.S, 0.0, s) ||
+        // both occupancy buffers start at zero; each stage zeroes the one it reads
+        if (launch_fill_f64(g, 5, 0.0, s) || launch_fill_f64(rho_a, 2L * (long)I.S, 0.0, s) ||
             launch_fill_f64(gpart, 5L * 1024, 0.0, s) ||
             (gstage && launch_fill_f64(gstage, (long)adjoint_grade_slots(), 0.0, s)) ||
             (gspat && launch_fill_f64(gspat, 2L * (long)adjoint_grade_slots() * I.n_lights, 0.0, s)))
@@ -1310,9 +1666,12 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
         for (int k = 1; k < I.N; k++) {
             const int L = I.light_of_stage[k];
             const TLEntry *tl = L >= 0 ? p->dev_tl + I.tl_dev_off + (size_t)L * I.P.n_t : nullptr;
-            if (launch_fill_f64(rho_b, (long)I.S, 0.0, s)) return hip_fail(hipGetLastError(), "fill launch");
+            void *tab = (char *)scratch + p->scr_adjtab;
+            if ((k == 1 || !I.same_tables[k - 1]) && launch_adjoint_table(I.P, k, tab, s))
+                return hip_fail(hipGetLastError(), "adjoint table launch");
             double *gspat_L = gspat && L >= 0 ? gspat + 2 * adjoint_grade_slots() * (size_t)L : nullptr;
-            if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, rho_a, rho_b, gpart,
+            if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, tab, rho_a, rho_b,
+                                     gpart,
                                      gstage, gspat_L, s))
                 return hip_fail(hipGetLastError(), "adjoint stage launch");
             double *t = rho_a;
@@ -1381,8 +1740,9 @@ int dp_device_check(dp_plan *p, void *stream)
     e = hipMemcpyAsync(p->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "device error word reset");
-    return fail(DP_EDEVICE, "device error word 0x%x:%s", w,
-                (w & kDevErrCellOffset) ? " a SoC cell offset did not fit its int8 record field" : "");
+    return fail(DP_EDEVICE, "device error word 0x%x:%s%s", w,
+                (w & kDevErrCellOffset) ? " a SoC cell offset did not fit its int8 record field;" : "",
+                (w & kDevErrWait) ? " a persistent sweep gave up waiting for a stage;" : "");
 }
 
 int dp_sweep_time(dp_plan *p, double *ms, int32_t *launches)
@@ -1425,6 +1785,7 @@ void dp_destroy(dp_plan *p)
     if (p->tfork) (void)hipEventDestroy(p->tfork);
     if (p->tjoin) (void)hipEventDestroy(p->tjoin);
     if (p->dev_tables) (void)hipFree(p->dev_tables);
+    if (p->dev_ptables) (void)hipFree(p->dev_ptables);
     if (p->dev_params) (void)hipFree(p->dev_params);
     delete p;
 }

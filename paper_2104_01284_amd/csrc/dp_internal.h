@@ -33,11 +33,17 @@ inline int sweep_threads(int JT, int n_t) { return (JT > 8 ? JT / 8 : 1) * 64 * 
 // Grouped sweep over a table of (instance, stage) jobs.
 int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_records, hipStream_t s);
 size_t lds_sweep_bytes(int JT, int H, int n_t);
+size_t lds_sweep_bytes_p(int JT, int H, int pitch, int threads);
 size_t lds_job_index_bytes(int njobs);
 int sweep_vgprs(int JT, int pitch);
 int launch_sweep_jobs(int JT, int pitch, int threads, const StageBase &B, int njobs, const int *item_begin,
                       int total, int *queue, int grid, size_t lds, hipStream_t s);
 int launch_combine_jobs(const StageBase &B, int njobs, long max_nodes, hipStream_t s);
+// The persistent multi-instance sweep of one kernel class (JT rows, LDS pitch).
+int launch_sweep_persist(int JT, int pitch, int threads, const StageBase &B, const DevInst *insts,
+                         const PersistQueues &Q, int grid, size_t lds, hipStream_t s);
+// Resident workgroups per CU of that kernel (0 if unknown).
+int persist_blocks_per_cu(int JT, int pitch, int threads, size_t lds);
 int launch_fill_i32(int *p, long n, int v, hipStream_t s);
 
 // Every instance's rollout in one launch (one wave each); offsets per instance.
@@ -46,9 +52,13 @@ int launch_rollout_jobs(const DevInst *insts, int n_inst, const void *pi, const 
 int launch_fill_f64(double *p, long n, double v, hipStream_t s);
 int launch_adjoint_root(const DevInst &P, const float *J1, const int16_t *u0, double *rho1, double *gacc,
                         double *gstage, hipStream_t s);
+// The stage table of the adjoint (per speed node and control) and one stage
+// of the occupancy sweep; rho is zeroed as it is read.
+size_t adjoint_table_bytes(const DevInst &P);
+int launch_adjoint_table(const DevInst &P, int k, void *tab, hipStream_t s);
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
-                         const double *rho, double *rho_next, double *gacc, double *gstage, double *gspat_L,
-                         hipStream_t s);
+                         const void *tab, double *rho, double *rho_next, double *gacc, double *gstage,
+                         double *gspat_L, hipStream_t s);
 // dspat[3 L + (0, 1, 2)] = dV/d(offset, red, cycle) of signal L from the
 // adjoint_grade_slots() slot pairs per signal in gspat.
 int launch_adjoint_spat(int n_lights, const double *gspat, const double *grad, double *dspat, hipStream_t s);

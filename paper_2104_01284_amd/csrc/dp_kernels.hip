@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(1024) k_sweep_naive(DevInst P, int k, const fl
             pu = -1;
             if (i == P.zero_row && P.wait && t.wc >= 0) {
                 const float *pw = Jn + ((long)i * ns + j) * nt + t.wc;
-                const float w = t.wcost + (t.wg32 * pw[0] + t.wf32 * pw[1]);
+                const float w = wait_value(t, pw);
                 if (w < Jinf) {
                     J = w;
                     pu = -2;

@@ -78,6 +78,15 @@ struct TLEntry {
     int32_t ncyc;  // whole cycles n in t_abs - O = n C + phase (dtau/dC = n)
 };
 
+// Value of waiting at a signal (the waiting cost plus the next stage's values
+// lerped at the time reached when red ends, pw pointing at the lower time
+// cell).  Written with explicit fused steps so that every kernel forming it
+// (sweep, control-slice combine, simple sweep) rounds the same way.
+__device__ __forceinline__ float wait_value(const TLEntry &t, const float *pw)
+{
+    return t.wcost + fmaf(t.wg32, pw[0], t.wf32 * pw[1]);
+}
+
 // One (instance, stage) of the grouped sweep.  Buffer positions are byte
 // offsets from the J, pi and scratch pointers of the call, so one table built
 // with the plan serves every call.
@@ -115,6 +124,32 @@ struct StageBase {
 
 // Bits of the plan's device error word (sticky until read by the host).
 constexpr int kDevErrCellOffset = 1;   // a SoC cell offset did not fit the records' int8 field
+constexpr int kDevErrWait = 2;         // a persistent sweep gave up waiting for a stage
+
+// One (instance, stage) job of the persistent sweep: the stage job, the items
+// of the instance's later stages that must be counted before it starts, and
+// its first item in its XCD queue.
+struct PJob {
+    StageJob j;
+    int need;
+    int item0;
+    int pad[2];
+};
+
+// Queues of one persistent sweep launch: per XCD a range of jobs and its item
+// count; claim counters per XCD and done counters per instance (scratch,
+// cleared before the launch).
+struct PersistQueues {
+    const PJob *jobs;
+    const int *xjb;        // [n_xcd + 1] job bounds of the XCD queues
+    const int *xtot;       // [n_xcd] items of each XCD queue
+    int *claim;            // [n_xcd]
+    int *done;             // [n_inst] items counted per instance
+    int *err;              // the plan's device error word
+    int n_xcd;
+    int stall;             // test hook: each queue's first job waits for a count never reached
+    long long spin_limit;  // polls (each followed by a short sleep) before a wait gives up
+};
 
 // Result of the continuous one-step model for (stage k, speed v, control).
 struct PT {

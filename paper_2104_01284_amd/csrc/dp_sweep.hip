@@ -384,77 +384,14 @@ constexpr int kStageRows = 8;
 // float, so that sums of two of them stay finite).
 constexpr float kPad = 1.7014118e38f;
 
-// The job and parameter tables come in as separate read-only arguments so
-// that their fields are loaded through the scalar unit.
-// 16-row tiles run three 8-wave workgroups per CU when a lane holds at most
-// 80 registers (six waves per SIMD): the compiler is held to that.
+// One item of the grouped sweep: speed node (by rank of work) x SoC tile x
+// control slice `item` of stage job `jb` (instance parameters PI), on the
+// workgroup's LDS `lds`; every thread of the workgroup calls it.
 template <int JT, int PITCH>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(JT == 16 ? 6 : 1, 8)))
-k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs, const DevInst *__restrict__ insts, int njobs,
-            const int *__restrict__ item_begin, int total, int *__restrict__ queue)
+__device__ __forceinline__ void sweep_item(const StageBase &B, const StageJob &jb, const DevInst &PI, int item,
+                                           float *lds)
 {
-    extern __shared__ float lds_base[];
     constexpr int CW = rec_words(JT);
-    // A launch covers the items of njobs jobs; item_begin[q] is the first
-    // item of job q (njobs + 1 entries, kept in LDS ahead of the planes).
-    int *s_ib = reinterpret_cast<int *>(lds_base);
-    const int ibw = item_begin ? ((njobs + 64) / 64) * 64 : 0;
-    if (item_begin)
-        for (int q = threadIdx.x; q <= njobs; q += blockDim.x) s_ib[q] = item_begin[q];
-    float *lds = lds_base + ibw;
-    // Persistent workgroups take (job, speed node, SoC tile, control slice)
-    // items from eight queues, one contiguous band of items per XCD (blocks
-    // are dealt round-robin over the 8 XCDs, so a band's next-stage planes
-    // stay in one L2); a job's speed nodes come in decreasing order of work,
-    // which keeps a band's nodes close in speed and leaves the shortest items
-    // for the end.  A workgroup whose band is drained takes items from the
-    // other bands; every workgroup exits once all queues are drained.  A
-    // launch with no more items than workgroups skips the queues.
-    __shared__ int s_item, s_job;
-    const int home = blockIdx.x & 7;
-    int qi = 0;
-    __syncthreads();
-    for (;;) {
-    if (threadIdx.x == 0) {
-        int item = -1, job = 0;
-        if (total <= (int)gridDim.x) {
-            // no more items than workgroups: workgroup b takes item b and
-            // leaves (a drained queue polled by every workgroup would cost
-            // more than the work)
-            if (qi == 0 && (int)blockIdx.x < total) item = blockIdx.x;
-            qi = 8;
-        }
-        while (qi < 8) {
-            const int x = (home + qi) & 7;
-            const int lo = (int)(((long)total * x) >> 3), hi = (int)(((long)total * (x + 1)) >> 3);
-            const int got = lo + atomicAdd(&queue[x], 1);
-            if (got < hi) {
-                item = got;
-                break;
-            }
-            qi++;
-        }
-        if (item >= 0 && item_begin) {
-            // the last job whose first item is <= item
-            int a = 0, b = njobs - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (s_ib[mid] <= item) a = mid;
-                else b = mid - 1;
-            }
-            job = a;
-            item -= s_ib[a];
-        }
-        s_item = item;
-        s_job = job;
-    }
-    __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
-    const int jbi = __builtin_amdgcn_readfirstlane(s_job);
-    __syncthreads();
-    if (item < 0) break;
-    const StageJob &jb = jobs[jbi];
-    const DevInst &PI = insts[jb.inst];
     SweepArgs P;
     P.n_v = PI.n_v;
     P.n_t = PI.n_t;
@@ -740,7 +677,7 @@ k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs, const DevInst *__res
                     pu = -1;
                     if (i == P.zero_row && P.wait && t.wc >= 0) {
                         const float *pw = Jn + ((long)i * ns + j) * nt + t.wc;
-                        const float w = t.wcost + (t.wg32 * pw[0] + t.wf32 * pw[1]);
+                        const float w = wait_value(t, pw);
                         if (w < Jinf) {
                             J = w;
                             pu = -2;
@@ -753,7 +690,158 @@ k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs, const DevInst *__res
             }
         }
     }
+}
+
+// The job and parameter tables come in as separate read-only arguments so
+// that their fields are loaded through the scalar unit.
+// 16-row tiles run three 8-wave workgroups per CU when a lane holds at most
+// 80 registers (six waves per SIMD): the compiler is held to that.
+template <int JT, int PITCH>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(JT == 16 ? 6 : 1, 8)))
+k_sweep_lds(StageBase B, const StageJob *__restrict__ jobs, const DevInst *__restrict__ insts, int njobs,
+            const int *__restrict__ item_begin, int total, int *__restrict__ queue)
+{
+    extern __shared__ float lds_base[];
+    // A launch covers the items of njobs jobs; item_begin[q] is the first
+    // item of job q (njobs + 1 entries, kept in LDS ahead of the planes).
+    int *s_ib = reinterpret_cast<int *>(lds_base);
+    const int ibw = item_begin ? ((njobs + 64) / 64) * 64 : 0;
+    if (item_begin)
+        for (int q = threadIdx.x; q <= njobs; q += blockDim.x) s_ib[q] = item_begin[q];
+    float *lds = lds_base + ibw;
+    // Persistent workgroups take (job, speed node, SoC tile, control slice)
+    // items from eight queues, one contiguous band of items per XCD (blocks
+    // are dealt round-robin over the 8 XCDs, so a band's next-stage planes
+    // stay in one L2); a job's speed nodes come in decreasing order of work,
+    // which keeps a band's nodes close in speed and leaves the shortest items
+    // for the end.  A workgroup whose band is drained takes items from the
+    // other bands; every workgroup exits once all queues are drained.  A
+    // launch with no more items than workgroups skips the queues.
+    __shared__ int s_item, s_job;
+    const int home = blockIdx.x & 7;
+    int qi = 0;
+    __syncthreads();
+    for (;;) {
+    if (threadIdx.x == 0) {
+        int item = -1, job = 0;
+        if (total <= (int)gridDim.x) {
+            // no more items than workgroups: workgroup b takes item b and
+            // leaves (a drained queue polled by every workgroup would cost
+            // more than the work)
+            if (qi == 0 && (int)blockIdx.x < total) item = blockIdx.x;
+            qi = 8;
+        }
+        while (qi < 8) {
+            const int x = (home + qi) & 7;
+            const int lo = (int)(((long)total * x) >> 3), hi = (int)(((long)total * (x + 1)) >> 3);
+            const int got = lo + atomicAdd(&queue[x], 1);
+            if (got < hi) {
+                item = got;
+                break;
+            }
+            qi++;
+        }
+        if (item >= 0 && item_begin) {
+            // the last job whose first item is <= item
+            int a = 0, b = njobs - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (s_ib[mid] <= item) a = mid;
+                else b = mid - 1;
+            }
+            job = a;
+            item -= s_ib[a];
+        }
+        s_item = item;
+        s_job = job;
+    }
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    const int jbi = __builtin_amdgcn_readfirstlane(s_job);
+    __syncthreads();
+    if (item < 0) break;
+    sweep_item<JT, PITCH>(B, jobs[jbi], insts[jobs[jbi].inst], item, lds);
     }   // item loop
+}
+
+// Persistent grouped sweep over every stage of many instances (the batched
+// solve in one launch per kernel class).  Each XCD has its own queue of
+// (instance, stage) jobs and the instances of a queue are served by the
+// workgroups running on that XCD only, which read the hardware XCC id: the
+// values a stage writes are then read by the next stage through the same
+// L2, so a workgroup publishes an item by waiting for its stores (vmcnt)
+// before it counts the item, and a workgroup that takes an item of stage k
+// waits (bounded) until the instance's items of stages N-1..k+1 are all
+// counted, then invalidates its CU's L1 before it reads J_{k+1}.  Within a
+// queue the jobs come round by round (stage N_b - 1 - r of every instance of
+// the queue in round r), so the items a wait depends on were all taken
+// earlier by running workgroups.  A wait that exceeds the spin limit, or an
+// error raised by another workgroup, makes every workgroup leave; the error
+// word then holds kDevErrWait.  4- and 16-row tiles are held to 80 registers
+// a lane (six waves per SIMD), as in the round-by-round sweep.
+template <int JT, int PITCH>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(JT == 8 ? 1 : 6, 8)))
+k_sweep_persist(StageBase B, const DevInst *__restrict__ insts, PersistQueues Q)
+{
+    extern __shared__ float lds[];
+    __shared__ int s_item, s_job;
+    int xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    const int x = (xcc & 0xf) % Q.n_xcd;
+    const int jb0 = Q.xjb[x], jb1 = Q.xjb[x + 1];
+    const int total = Q.xtot[x];
+    int jcur = jb0;       // thread 0: job of its last claim (claims only grow)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int item = -1, job = -1;
+            if (jb0 < jb1 && __hip_atomic_load(Q.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                const int g = atomicAdd(Q.claim + x, 1);
+                if (g < total) {
+                    while (jcur + 1 < jb1 && Q.jobs[jcur + 1].item0 <= g) jcur++;
+                    const PJob &pj = Q.jobs[jcur];
+                    const int need = pj.need;
+                    int *done = Q.done + pj.j.inst;
+                    // the test hook: the queue's first job also waits for a
+                    // count nothing ever reaches
+                    const bool stall = Q.stall && jcur == jb0;
+                    long long spins = 0;
+                    bool ok = true;
+                    while (stall || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (++spins > Q.spin_limit ||
+                            __hip_atomic_load(Q.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            atomicOr(Q.err, kDevErrWait);
+                            ok = false;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    if (ok) {
+                        job = jcur;
+                        item = g - pj.item0;
+                    }
+                }
+            }
+            s_item = item;
+            s_job = job;
+        }
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        __syncthreads();
+        if (item < 0) break;
+        // every wave drops its CU's L1 copies before it reads, so that J_{k+1}
+        // comes from the XCD's L2, which holds the other workgroups' stores.
+        // The invalidate must be of device scope: the workgroup-scope form
+        // leaves the L1 of a workgroup that runs on one CU untouched (measured:
+        // with it the last stages of an instance read stale J_{k+1} lines)
+        asm volatile("buffer_inv sc1" ::: "memory");
+        const PJob &pj = Q.jobs[job];
+        sweep_item<JT, PITCH>(B, pj.j, insts[pj.j.inst], item, lds);
+        // every store of the item has reached the L2 before the item counts
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(Q.done + pj.j.inst, 1);
+    }
 }
 
 // Minimum over the control splits (the first split wins a tie, so the result
@@ -793,7 +881,7 @@ __global__ void k_sweep_combine(StageBase B)
                 pu = -1;
                 if (i == P.zero_row && P.wait && t.wc >= 0) {
                     const float *pw = Jn + ij * P.n_t + t.wc;
-                    const float w = t.wcost + (t.wg32 * pw[0] + t.wf32 * pw[1]);
+                    const float w = wait_value(t, pw);
                     if (w < Jinf) {
                         J = w;
                         pu = -2;
@@ -817,6 +905,11 @@ int launch_stage_jobs(const StageBase &B, int njobs, int max_nv, long max_record
     hipLaunchKernelGGL(k_stage_bat_sorted, dim3((unsigned)((max_records + 255) / 256), njobs), dim3(256), 0, s, B);
     // (max_records counts record lanes: records x SoC rows per record)
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+size_t lds_sweep_bytes_p(int JT, int H, int pitch, int threads)
+{
+    return sizeof(float) * (2 * (size_t)sweep_rows(JT, H) * pitch + (size_t)kPrefetch * threads + 16);
 }
 
 size_t lds_sweep_bytes(int JT, int H, int n_t)
@@ -926,6 +1019,91 @@ static int sweep_vgprs_p(int pitch)
     if (e == hipSuccess && a.numRegs > 0) return a.numRegs;
     (void)hipGetLastError();
     return JT == 16 ? 128 : (JT == 8 ? 96 : 80);
+}
+
+template <int JT>
+static int launch_persist_p(int pitch, dim3 grid, dim3 block, size_t lds, hipStream_t s, const StageBase &B,
+                            const DevInst *insts, const PersistQueues &Q)
+{
+    switch (pitch) {
+#define ECODP_PITCH(X)                                                                            \
+    case X:                                                                                       \
+        hipLaunchKernelGGL((k_sweep_persist<JT, X>), grid, block, lds, s, B, insts, Q);          \
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+        ECODP_PITCH(32)
+        ECODP_PITCH(64)
+        ECODP_PITCH(96)
+        ECODP_PITCH(128)
+        ECODP_PITCH(160)
+        ECODP_PITCH(192)
+        ECODP_PITCH(224)
+        ECODP_PITCH(256)
+        ECODP_PITCH(288)
+        ECODP_PITCH(320)
+        ECODP_PITCH(352)
+        ECODP_PITCH(384)
+        ECODP_PITCH(416)
+        ECODP_PITCH(448)
+        ECODP_PITCH(480)
+        ECODP_PITCH(512)
+#undef ECODP_PITCH
+    default: return -2;
+    }
+}
+
+template <int JT>
+static int persist_blocks_p(int pitch, int threads, size_t lds)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (pitch) {
+#define ECODP_PITCH(X)                                                                                       \
+    case X:                                                                                                  \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_sweep_persist<JT, X>), \
+                                                         threads, lds);                                      \
+        break;
+        ECODP_PITCH(32)
+        ECODP_PITCH(64)
+        ECODP_PITCH(96)
+        ECODP_PITCH(128)
+        ECODP_PITCH(160)
+        ECODP_PITCH(192)
+        ECODP_PITCH(224)
+        ECODP_PITCH(256)
+        ECODP_PITCH(288)
+        ECODP_PITCH(320)
+        ECODP_PITCH(352)
+        ECODP_PITCH(384)
+        ECODP_PITCH(416)
+        ECODP_PITCH(448)
+        ECODP_PITCH(480)
+        ECODP_PITCH(512)
+#undef ECODP_PITCH
+    default: break;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+int persist_blocks_per_cu(int JT, int pitch, int threads, size_t lds)
+{
+    if (JT == 8) return persist_blocks_p<8>(pitch, threads, lds);
+    if (JT == 4) return persist_blocks_p<4>(pitch, threads, lds);
+    if (JT == 16) return persist_blocks_p<16>(pitch, threads, lds);
+    return 0;
+}
+
+int launch_sweep_persist(int JT, int pitch, int threads, const StageBase &B, const DevInst *insts,
+                         const PersistQueues &Q, int grid, size_t lds, hipStream_t s)
+{
+    const dim3 g(grid), blk(threads);
+    if (JT == 8) return launch_persist_p<8>(pitch, g, blk, lds, s, B, insts, Q);
+    if (JT == 4) return launch_persist_p<4>(pitch, g, blk, lds, s, B, insts, Q);
+    if (JT == 16) return launch_persist_p<16>(pitch, g, blk, lds, s, B, insts, Q);
+    return -2;
 }
 
 int sweep_vgprs(int JT, int pitch)

@@ -121,6 +121,29 @@ def load_golden(name, inst):
     return g if g.get("digest") == instances.digest(inst) else None
 
 
+def batch_golden_report(insts, V0, u0):
+    """V_0 and u_0 of the batch members with stored FP64 oracle results
+    (tests/golden/batched_oracle.json, each member digest-checked against
+    `insts`) against those results; None when the file is missing."""
+    import json
+    from . import instances
+    path = os.path.join(GOLDEN_DIR, "batched_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    errs, mism, stale = [], 0, 0
+    for m in g["members"]:
+        b = int(m["member"])
+        if b >= len(insts) or instances.digest(insts[b]) != m["digest"]:
+            stale += 1
+            continue
+        errs.append(abs(float(V0[b]) - m["V0"]) / abs(m["V0"]))
+        mism += int(int(u0[b]) != int(m["u0"]))
+    return {"members": len(errs), "stale_members": stale,
+            "V0_max_rel_err": max(errs) if errs else None, "u0_mismatch": mism}
+
+
 def _rel(a, b):
     return abs(a - b) / max(1.0, abs(b))
 

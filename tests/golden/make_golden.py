@@ -1,7 +1,7 @@
 """Write the stored oracle values used by the GPU parity tests at full size.
 
 Calls only the FP64 oracle and the seeded instance generator.  Run from the
-repository root:  python tests/golden/make_golden.py [realistic] [large]
+repository root:  python tests/golden/make_golden.py [realistic] [large] [batched]
 The 2 km instance takes about ten minutes on 6 host threads, the 3 km one
 (1.7e12 evaluations, about 20 GB of host memory for the stored values and
 policy) about two hours.
@@ -100,6 +100,38 @@ def make(name, per_stage=256, seed=123):
     print(f"wrote {path}: V0={r['V0']:.6f} u0={r['u0']} in {dt:.1f}s", flush=True)
 
 
+def batch_subset(n=256):
+    """Stratified members of the 256-instance batch: the smallest and the
+    largest by evaluations, and every 16th."""
+    work = sorted((ins.evaluations(ins.batched_member(b)), b) for b in range(n))
+    return sorted({work[0][1], work[-1][1]} | set(range(0, n, 16)))
+
+
+def make_batched():
+    """V_0, u_0* and the second-best root candidate of the stratified batch
+    members (FP64 oracle)."""
+    import oracle
+    rows = []
+    t = time.time()
+    for b in batch_subset():
+        inst = ins.batched_member(b)
+        r = oracle.solve(inst)
+        # the second-best root candidate: where it is within the FP32
+        # tolerance of V_0, another u_0 is an admissible answer
+        _, _, q2 = oracle.root(inst, r["J"][1])
+        rows.append({"member": b, "instance": inst["name"], "digest": instance_digest(inst),
+                     "V0": r["V0"], "u0": r["u0"], "q2_root": q2, "evaluations": ins.evaluations(inst)})
+        print(f"batched member {b}: V0={r['V0']:.9f} u0={r['u0']} q2={q2:.9f}", flush=True)
+        del r
+    out = {"source": "oracle.solve (FP64) on paper_2104_01284_amd.instances.batched_member(b)",
+           "members": rows, "oracle_seconds": time.time() - t, "oracle_threads": oracle.num_threads()}
+    path = os.path.join(HERE, "batched_oracle.json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(path + ".tmp", path)
+    print(f"wrote {path}", flush=True)
+
+
 def load(name):
     """The stored file for instance `name` if its digest matches today's
     generator, else None (reads JSON only)."""
@@ -115,4 +147,7 @@ def load(name):
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or ["realistic"]):
-        make(name)
+        if name == "batched":
+            make_batched()
+        else:
+            make(name)

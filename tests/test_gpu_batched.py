@@ -1,9 +1,10 @@
-"""GPU: the batched solve (all instances in rounds of one stage each), its
-HIP-graph replay and per-instance sweep configurations.
+"""GPU: the batched solve (the persistent multi-instance sweep, and rounds of
+one stage each), its HIP-graph replay and per-instance sweep configurations.
 
 A batch must reproduce every instance's single solve bit for bit: each node's
 candidates are computed by the same arithmetic whatever the batch, the
-control slices are combined first-minimum in visit order, and exact FP32
+control slices are combined first-minimum in visit order (the persistent
+sweep takes no slices: one pass keeps the same first minimum), and exact FP32
 minima do not depend on the order the work items run in.  Against the FP64
 oracle the tolerances of the single-instance parity tests apply.
 """
@@ -70,14 +71,39 @@ def assert_batch_equals_single(torch, big, insts, **kw):
         assert torch.equal(big.policy(b), one.policy(0)), (b, inst["name"])
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
-def test_batch_rounds_equal_single_solves(torch, kernel):
+@pytest.mark.parametrize("kernel,rounds", [(1, False), (2, False), (2, True)])
+def test_batch_equals_single_solves(torch, kernel, rounds):
+    """The batch in one persistent sweep (the default) and in rounds of
+    launches, against every instance's single solve."""
     insts = small_batch()
-    say("batch of", len(insts), "kernel", kernel)
-    big = Plan(insts, store_all=True, kernel=kernel)
+    say("batch of", len(insts), "kernel", kernel, "rounds", rounds)
+    big = Plan(insts, store_all=True, kernel=kernel, rounds=rounds)
     big.solve()
     torch.cuda.synchronize()
+    big.device_check()
     assert_batch_equals_single(torch, big, insts, kernel=kernel)
+
+
+def test_persistent_wait_gives_up_on_stall(torch):
+    """The persistent sweep's bounded wait, forced from the host: with the
+    test hook every queue's first job waits for a count nothing reaches; the
+    wait gives up after its poll limit, every workgroup leaves, the device
+    error word is set and dp_device_check reports it; a plan without the hook
+    then solves normally."""
+    from paper_2104_01284_amd._lib import DPError
+    insts = small_batch()
+    bad = Plan(insts, store_all=True, stall_test=True)
+    bad.solve()
+    torch.cuda.synchronize()
+    with pytest.raises(DPError) as e:
+        bad.device_check()
+    assert "gave up" in str(e.value)
+    bad.device_check()                  # the word was cleared
+    good = Plan(insts, store_all=True)
+    good.solve()
+    torch.cuda.synchronize()
+    good.device_check()
+    assert_batch_equals_single(torch, good, insts)
 
 
 def test_batch_against_oracle(torch):
@@ -221,3 +247,48 @@ def test_full_batch_sampled(torch):
             assert abs(J0[i, j, m] - Jo) <= REL_J * max(1.0, abs(Jo)), (b, i, j, m, J0[i, j, m], Jo)
             if p0[i, j, m] != po:
                 assert q2 - Jo < REL_GAP * max(1.0, abs(Jo)), (b, i, j, m)
+
+
+def test_full_batch_against_stored_oracle_and_rollouts(torch):
+    """The full 256-instance batch as the benchmark times it (persistent
+    sweep, HIP graph) against the stored FP64 oracle results of its
+    stratified subset (tests/golden/batched_oracle.json, each member
+    digest-checked): V_0 within 1e-4 relative, and u_0* equal to the oracle's
+    unless the oracle's second-best root candidate is within 1e-4 max(1, |V_0|)
+    of V_0.  Then the batch's rollouts (one launch, one wave per instance)
+    against each subset member's single-plan rollout, bit for bit."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_oracle.json")
+    with open(path) as f:
+        g = json.load(f)
+    insts = ins.batched(256)
+    big = Plan(insts, store_all=False, graph=True)
+    assert all(int(i.sweep_persistent) == 1 for i in big.info)
+    V0, u0 = big.solve()
+    torch.cuda.synchronize()
+    big.device_check()
+    checked = 0
+    for m in g["members"]:
+        b = int(m["member"])
+        assert ins.digest(insts[b]) == m["digest"], b      # the stored results are of today's generator
+        rel = abs(float(V0[b]) - m["V0"]) / abs(m["V0"])
+        say("member", b, "V0 gpu", float(V0[b]), "oracle", m["V0"], "rel", rel, "u0", int(u0[b]), m["u0"])
+        assert rel <= 1e-4, b
+        if int(u0[b]) != int(m["u0"]):
+            assert "q2_root" in m and m["q2_root"] - m["V0"] < 1e-4 * max(1.0, abs(m["V0"])), b
+        checked += 1
+    assert checked == len(g["members"]) >= 16
+    trajs, status = big.rollout()
+    torch.cuda.synchronize()
+    for m in g["members"]:
+        b = int(m["member"])
+        one = Plan([insts[b]], store_all=False)
+        one.solve()
+        t1, s1 = one.rollout()
+        torch.cuda.synchronize()
+        a, c = trajs[b], t1[0]
+        same = (a == c) | (torch.isnan(a) & torch.isnan(c))     # the last row's control fields are NaN
+        assert bool(same.all()), b
+        assert torch.equal(status[b], s1[0]), b
+        del one
