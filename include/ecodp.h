@@ -223,6 +223,75 @@ int dp_terminal_from_values(const float *src, int32_t n_v, int32_t n_soc, int32_
                             double t_f_src, double t_shift, int32_t n_t_dst, double t_f_dst,
                             double J_inf, float *dst, void *stream);
 
+/* The closed-loop receding-horizon controller (Sec. V, Sec. III after Eq. 9)
+ * along one route, kept in the library.  dp_loop_create copies the route
+ * (n_stages N_route, grade, speed limits, signals, x0 and clock t0_abs, the
+ * route's own terminal cost) and solves it once over the whole route
+ * (DP_STORE_ALL_V): the offline DP whose value slabs give every horizon its
+ * terminal cost.  It then builds one plan per horizon length
+ * N = 1 .. min(horizon, N_route), each on the time grid [0, t_f] x n_t with
+ * the route's speed, SoC and control grids and w_soc = 0, kept for the whole
+ * drive.  opt: kernel and tile choices for the horizon plans (NULL = automatic);
+ * of its flags only DP_TIMING is used (the summed sweep time of every step in
+ * dp_loop_totals; without it the horizon solves are recorded as HIP graphs
+ * and replayed).  All device memory is allocated here, none per step.
+ *
+ * dp_loop_step drives one route stage s from the state (v, soc, t_abs):
+ *   1. a vehicle at rest (v == 0) at the stop line of a signal of stage s
+ *      that shows red (Eq. 8: red iff (t_abs - O) mod C < R) waits for green
+ *      (Eq. 5c): t_abs and the trip's waiting time grow by the rest of the red
+ *      phase and the trip cost by w_t times it;
+ *   2. the horizon of the next N = min(horizon, N_route - s) steps (grades
+ *      s..s+N-1, limits s..s+N, the signals strictly inside, re-indexed from
+ *      s) is written into the kept plan of length N in place, with x0 =
+ *      (v, soc) and clock t_abs;
+ *   3. its terminal table is the offline value slab J_{s+N} shifted by
+ *      t_abs - t0_abs (dp_terminal_from_values);
+ *   4. dp_solve and dp_rollout; the rollout's first step, under u_0*, is the
+ *      plant step (exact FP64 dynamics, Eq. 1-2, 5a-b);
+ *   5. the vehicle moves to stage s+1: (v, soc) from that step, t_abs + dt;
+ *      fuel and cost of the step are added to the trip; arriving above the
+ *      speed limit of stage s+1, or moving (v > 0) at a signal of stage s+1
+ *      during red, counts one violation each; a SoC off the grid, no
+ *      admissible control (u_0* = -1) or a non-finite step stops the loop
+ *      with status DP_EINFEASIBLE.
+ * The row describes the step; its status is the loop's.  After the last
+ * stage, or once stopped, dp_loop_step returns DP_ESTATE.  A loop must not be
+ * used from two host threads at once. */
+typedef struct dp_loop dp_loop;
+
+typedef struct {
+    int32_t stage;             /* route stage s of the step                                         */
+    double t_abs, v, soc;      /* clock [s] and state at the solve (after any wait)                */
+    double wait_s;             /* seconds waited at the stop line before the solve                 */
+    int32_t horizon;           /* N of the step's horizon                                          */
+    int64_t evaluations;       /* state-control evaluations of its solve (N n_v n_soc n_t n_u)     */
+    float V0;                  /* V_0 of the horizon                                               */
+    int32_t u0;                /* applied control u_0* (-1: none)                                  */
+    double v1, soc1, dt;       /* the plant step under u_0*                                        */
+    double fuel_g, cost;       /* fuel [g] and cost of the step                                    */
+    int32_t violations;        /* violations counted at arrival at stage s+1 (0, 1 or 2)           */
+    int32_t status;            /* DP_OK, or DP_EINFEASIBLE when the loop stopped at this step       */
+} dp_loop_row;
+
+typedef struct {
+    int32_t stage;             /* route stage of the vehicle                                        */
+    double t_abs, v, soc;      /* current clock and state                                           */
+    double fuel_g, cost, wait_s;
+    int32_t violations;
+    int32_t status;            /* DP_OK, or DP_EINFEASIBLE once stopped                             */
+    int32_t steps;             /* steps driven                                                      */
+    double offline_ms;         /* host time of dp_loop_create's full-route solve                    */
+    double sweep_ms;           /* with DP_TIMING: summed state-sweep launch time of all steps       */
+    int32_t sweep_launches;
+} dp_loop_totals;
+
+int dp_loop_create(const dp_problem_desc *route, int32_t horizon, double t_f, int32_t n_t,
+                   const dp_options *opt, int32_t device, dp_loop **out);
+int dp_loop_step(dp_loop *loop, dp_loop_row *row);
+int dp_loop_get_totals(const dp_loop *loop, dp_loop_totals *totals);
+void dp_loop_destroy(dp_loop *loop);
+
 /* Forward rollout of the stored policy from x0 with exact FP64 dynamics.
  * traj_dev: double rows [v, xi, t, u, T_eng, T_mot, fuel_g, cost] for stages
  * 0..N of every instance (offset dp_instance_info.traj_offset); the last row's

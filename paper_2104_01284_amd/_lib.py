@@ -24,6 +24,7 @@ DP_STALL_TEST = 16
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_solve_static",
            "dp_stage", "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_adjoint_grade",
            "dp_adjoint_spat", "dp_executed_evaluations", "dp_device_check", "dp_sweep_time", "dp_destroy",
+           "dp_loop_create", "dp_loop_step", "dp_loop_get_totals", "dp_loop_destroy",
            "dp_status_string", "dp_last_error")
 
 
@@ -59,6 +60,20 @@ class DpInstanceInfo(C.Structure):
                 ("sweep_grid", C.c_int32), ("soc_shift", C.c_int32), ("sweep_persistent", C.c_int32)]
 
 
+class DpLoopRow(C.Structure):
+    _fields_ = [("stage", C.c_int32), ("t_abs", C.c_double), ("v", C.c_double), ("soc", C.c_double),
+                ("wait_s", C.c_double), ("horizon", C.c_int32), ("evaluations", C.c_int64), ("V0", C.c_float),
+                ("u0", C.c_int32), ("v1", C.c_double), ("soc1", C.c_double), ("dt", C.c_double),
+                ("fuel_g", C.c_double), ("cost", C.c_double), ("violations", C.c_int32), ("status", C.c_int32)]
+
+
+class DpLoopTotals(C.Structure):
+    _fields_ = [("stage", C.c_int32), ("t_abs", C.c_double), ("v", C.c_double), ("soc", C.c_double),
+                ("fuel_g", C.c_double), ("cost", C.c_double), ("wait_s", C.c_double),
+                ("violations", C.c_int32), ("status", C.c_int32), ("steps", C.c_int32),
+                ("offline_ms", C.c_double), ("sweep_ms", C.c_double), ("sweep_launches", C.c_int32)]
+
+
 _lib = None
 
 
@@ -92,6 +107,12 @@ def load(require_torch: bool = True):
     lib.dp_sweep_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     lib.dp_destroy.argtypes = [vp]
     lib.dp_destroy.restype = None
+    lib.dp_loop_create.argtypes = [C.POINTER(DpProblemDesc), C.c_int32, C.c_double, C.c_int32,
+                                   C.POINTER(DpOptions), C.c_int32, C.POINTER(vp)]
+    lib.dp_loop_step.argtypes = [vp, C.POINTER(DpLoopRow)]
+    lib.dp_loop_get_totals.argtypes = [vp, C.POINTER(DpLoopTotals)]
+    lib.dp_loop_destroy.argtypes = [vp]
+    lib.dp_loop_destroy.restype = None
     lib.dp_status_string.argtypes = [C.c_int]
     lib.dp_status_string.restype = C.c_char_p
     lib.dp_last_error.argtypes = [C.c_char_p, sz]

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libecodp.so")
-SOURCES = ["dp_api.hip", "dp_kernels.hip", "dp_sweep.hip", "dp_adjoint.hip"]
+SOURCES = ["dp_api.hip", "dp_kernels.hip", "dp_sweep.hip", "dp_adjoint.hip", "dp_loop.hip"]
 ARCH = os.environ.get("ECODP_ARCH", "gfx950")
 
 

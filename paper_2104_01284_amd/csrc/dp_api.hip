@@ -39,6 +39,14 @@ int hip_fail(hipError_t e, const char *what)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Set while build_window_plan builds a closed loop's window plan: every stage
+// builds its own tables, and the SoC-shift bound is at least h_min.
+struct WindowBuild {
+    bool on = false;
+    int h_min = 0;
+};
+thread_local WindowBuild t_window;
+
 struct Inst {
     DevInst P;                 // device pointers filled at build
     int N = 0;
@@ -985,7 +993,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         // the stage tables of k depend on k only through the grade of step k
         // and the speed limits at k and k+1
         I.same_tables.assign(N, 0);
-        for (int k = 0; k + 1 < N; k++)
+        for (int k = 0; k + 1 < N && !t_window.on; k++)
             I.same_tables[k] = cosa[b][k] == cosa[b][k + 1] && sina[b][k] == sina[b][k + 1] &&
                                vmax[b][k] == vmax[b][k + 1] && vmax[b][k + 1] == vmax[b][k + 2];
         I.l_cycle = lc[b];
@@ -1004,7 +1012,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         traj_off += (size_t)(N + 1) * 8;
         // state-sweep variant: the grouped LDS kernel when its tables and
         // staged planes fit, else the simple per-node kernel
-        I.H = soc_shift_bound(P, d);
+        I.H = std::max(soc_shift_bound(P, d), t_window.h_min);
         // SoC rows per workgroup: 8-row tiles when they leave five resident
         // waves per SIMD (the sweep waits on LDS and barriers, so resident
         // waves matter more than the per-tile saving), in a batch too (256
@@ -1045,6 +1053,14 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
                 if (t > 4 && d.n_soc < t) continue;
                 if (t == 16 && n_inst > 1) continue;   // measured slower in a batch
                 const double w = waves_per_simd(t);
+                if (n_inst > 1 && t == 8 && w > 0.0) {
+                    // a batch takes 8-row tiles wherever they fit: instances
+                    // with one tile share the kernel classes of the persistent
+                    // sweep (more classes than streams run one after another;
+                    // 256 solves: 1266 ms all on 8-row tiles, 1677 ms mixed)
+                    jt = t;
+                    break;
+                }
                 if (w >= min_waves) {
                     jt = t;
                     break;
@@ -1555,20 +1571,11 @@ int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_
     return DP_OK;
 }
 
-int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs, void *stream)
+// The plan's pinned staging buffer with at least `need` bytes, free to write:
+// the previous upload from it has run.
+static int state_staging(dp_plan *p, size_t need)
 {
-    if (!p) return fail(DP_EINVAL, "plan is NULL");
-    if (inst < 0 || inst >= (int)p->inst.size()) return fail(DP_EINVAL, "instance %d out of range", inst);
-    Inst &I = p->inst[inst];
-    if (!(std::isfinite(v0) && v0 >= 0.0 && std::isfinite(soc0) && soc0 >= I.P.s_lo && soc0 <= I.P.s_hi &&
-          std::isfinite(t0_abs)))
-        return fail(DP_EINVAL, "instance %d: x0 outside the grid or not finite", inst);
-    hipError_t e = hipSetDevice(p->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    hipStream_t s = (hipStream_t)stream;
-    const int nl = (int)I.l_cycle.size();
-    const size_t tl_n = (size_t)nl * I.P.n_t;
-    const size_t need = align_up(sizeof(DevInst), 256) + sizeof(TLEntry) * (tl_n ? tl_n : 1);
+    hipError_t e;
     if (p->state_pending) {
         // the staging buffer is read by the previous upload until it has run
         if ((e = hipEventSynchronize(p->state_ev)) != hipSuccess) return hip_fail(e, "state upload wait");
@@ -1584,6 +1591,25 @@ int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs
     }
     if (!p->state_ev && (e = hipEventCreateWithFlags(&p->state_ev, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "state event");
+    return DP_OK;
+}
+
+int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs, void *stream)
+{
+    if (!p) return fail(DP_EINVAL, "plan is NULL");
+    if (inst < 0 || inst >= (int)p->inst.size()) return fail(DP_EINVAL, "instance %d out of range", inst);
+    Inst &I = p->inst[inst];
+    if (!(std::isfinite(v0) && v0 >= 0.0 && std::isfinite(soc0) && soc0 >= I.P.s_lo && soc0 <= I.P.s_hi &&
+          std::isfinite(t0_abs)))
+        return fail(DP_EINVAL, "instance %d: x0 outside the grid or not finite", inst);
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const int nl = (int)I.l_cycle.size();
+    const size_t tl_n = (size_t)nl * I.P.n_t;
+    const size_t need = align_up(sizeof(DevInst), 256) + sizeof(TLEntry) * (tl_n ? tl_n : 1);
+    int rc = state_staging(p, need);
+    if (rc) return rc;
     I.P.v0 = v0;
     I.P.soc0 = soc0;
     I.P.t0_abs = t0_abs;
@@ -1601,6 +1627,7 @@ int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs
     p->solved = false;
     return DP_OK;
 }
+
 
 int dp_terminal_from_values(const float *src, int32_t n_v, int32_t n_soc, int32_t n_t_src, double t_f_src,
                             double t_shift, int32_t n_t_dst, double t_f_dst, double J_inf, float *dst, void *stream)
@@ -1791,3 +1818,93 @@ void dp_destroy(dp_plan *p)
 }
 
 }  // extern "C"
+
+namespace ecodp {
+
+int api_fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int build_window_plan(const dp_problem_desc &d, int H_min, const dp_options *opt, int device, dp_plan **out)
+{
+    t_window.on = true;
+    t_window.h_min = H_min;
+    const int rc = dp_build_problem(&d, 1, opt, device, out);
+    t_window = WindowBuild();
+    return rc;
+}
+
+float *plan_terminal(dp_plan *p) { return p ? const_cast<float *>(p->inst[0].P.terminal_V) : nullptr; }
+
+int plan_set_window(dp_plan *p, const double *grade, const double *vmax, const double *cycle, const double *red,
+                    const double *offset, double t0_abs, double v0, double soc0, hipStream_t s)
+{
+    Inst &I = p->inst[0];
+    const int N = I.N, nl = (int)I.l_cycle.size();
+    if (nl != N - 1) return fail(DP_ESTATE, "not a window plan (%d signals on %d stages)", nl, N);
+    if (!(std::isfinite(v0) && v0 >= 0.0 && std::isfinite(soc0) && soc0 >= I.P.s_lo && soc0 <= I.P.s_hi &&
+          std::isfinite(t0_abs)))
+        return fail(DP_EINVAL, "window: x0 outside the grid or not finite");
+    for (int k = 0; k < N; k++)
+        if (!std::isfinite(grade[k])) return fail(DP_EINVAL, "window: grade %d not finite", k);
+    for (int k = 0; k <= N; k++)
+        if (!(std::isfinite(vmax[k]) && vmax[k] >= 0.0)) return fail(DP_EINVAL, "window: speed limit %d", k);
+    for (int L = 0; L < nl; L++)
+        if (!(std::isfinite(cycle[L]) && cycle[L] > 0.0 && std::isfinite(red[L]) && red[L] >= 0.0 &&
+              red[L] <= cycle[L] && std::isfinite(offset[L])))
+            return fail(DP_EINVAL, "window: signal of stage %d", L + 1);
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    // the parameter block's per-stage arrays, in the layout of the build:
+    // cos and sin of the grade angle [N], speed limits [N+1], cycle, red and
+    // offset of every signal, three spare zeros
+    const size_t n_dbl = 3 * (size_t)N + 1 + 3 * (size_t)nl + 3;
+    const size_t tl_n = (size_t)nl * I.P.n_t;
+    const size_t o_dbl = align_up(sizeof(DevInst), 256);
+    const size_t o_tl = o_dbl + align_up(sizeof(double) * n_dbl, 256);
+    int rc = state_staging(p, o_tl + sizeof(TLEntry) * (tl_n ? tl_n : 1));
+    if (rc) return rc;
+    char *h = (char *)p->state_host;
+    double *dbl = (double *)(h + o_dbl);
+    for (int k = 0; k < N; k++) {
+        const double G = grade[k];
+        dbl[k] = 1.0 / std::sqrt(1.0 + G * G);
+        dbl[N + k] = G * dbl[k];
+    }
+    for (int k = 0; k <= N; k++) dbl[2 * N + k] = vmax[k];
+    for (int L = 0; L < nl; L++) {
+        dbl[3 * N + 1 + L] = cycle[L];
+        dbl[3 * N + 1 + nl + L] = red[L];
+        dbl[3 * N + 1 + 2 * nl + L] = offset[L];
+    }
+    for (int q = 0; q < 3; q++) dbl[3 * N + 1 + 3 * nl + q] = 0.0;
+    I.l_cycle.assign(cycle, cycle + nl);
+    I.l_red.assign(red, red + nl);
+    I.l_off.assign(offset, offset + nl);
+    I.P.v0 = v0;
+    I.P.soc0 = soc0;
+    I.P.t0_abs = t0_abs;
+    std::memcpy(h, &I.P, sizeof(DevInst));
+    TLEntry *htl = (TLEntry *)(h + o_tl);
+    for (int L = 0; L < nl; L++)
+        build_tl(cycle[L], red[L], offset[L], t0_abs, I.P.t_f, I.P.n_t, I.P.wt, htl + (size_t)L * I.P.n_t);
+    e = hipMemcpyAsync(p->dev_insts, h, sizeof(DevInst), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<double *>(I.P.cosa), dbl, sizeof(double) * n_dbl, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && tl_n)
+        e = hipMemcpyAsync(p->dev_tl + I.tl_dev_off, htl, sizeof(TLEntry) * tl_n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(p->state_ev, s);
+    if (e != hipSuccess) return hip_fail(e, "window upload");
+    p->state_pending = true;
+    p->solved = false;
+    return DP_OK;
+}
+
+}  // namespace ecodp

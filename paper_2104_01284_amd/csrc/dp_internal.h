@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/ecodp.h"
 #include "dp_model.h"
 
 namespace ecodp {
@@ -68,5 +69,22 @@ size_t adjoint_grade_slots();
 // doubles, zeroed before the first stage); grad += their sum.
 int launch_adjoint_reduce(const double *gpart, double *grad, hipStream_t s);
 int launch_adjoint_terminal(const DevInst &P, const float *JN, const double *rho, double *gacc, hipStream_t s);
+
+// ---- plans kept by a closed loop (dp_loop.hip) ----
+// Records the error message dp_last_error reports; returns code.
+int api_fail(int code, const char *fmt, ...);
+// A one-instance plan of a horizon window: built like dp_build_problem, but
+// every stage builds its own tables (the window moves along a route) and the
+// SoC-shift bound is at least H_min (the route's).  The description must carry
+// a signal at every stage 1..N-1 (placeholders until plan_set_window).
+int build_window_plan(const dp_problem_desc &d, int H_min, const dp_options *opt, int device, dp_plan **out);
+// Moves a window plan to another window of its route in place: grade [N],
+// speed limits [N+1], per stage 1..N-1 a signal (cycle, red, offset; red = 0
+// for a stage without one), clock and initial state, uploaded through the
+// plan's pinned staging on stream s.  Recorded graphs pick it up on replay.
+int plan_set_window(dp_plan *p, const double *grade, const double *vmax, const double *cycle, const double *red,
+                    const double *offset, double t0_abs, double v0, double soc0, hipStream_t s);
+// The plan's own device copy of its terminal table (DP_TERMINAL_DEVICE), or NULL.
+float *plan_terminal(dp_plan *p);
 
 }  // namespace ecodp

@@ -6,42 +6,25 @@ u_0* is applied to the vehicle, and the horizon moves on.  Its terminal cost
 is the value function of an offline DP over the whole route (Sec. III, after
 Eq. 9), and Table I reports the solver time of these re-solves.
 
-``ClosedLoop(route)`` solves the full route once on the GPU (``store_all``),
-then ``run()`` steps along it: per stage s it
-
-1. lets a vehicle stopped at the stop line of a red signal wait for green
-   (Eq. 5c, Eq. 8);
-2. builds the horizon problem of the next N = min(20, N_route - s) steps
-   (``instances.mpc_window``) with the current state and clock;
-3. derives its terminal table from the full-route value slab J_{s+N} on the
-   GPU (``dp_terminal_from_values``), handed to the plan as a device table;
-4. builds the plan, solves it, and runs the FP64 rollout, whose first step
-   is the plant step under u_0* (Eq. 1-2, 5a-b);
-5. reads the next state back and advances the clock.
-
-Every numerical step runs in libecodp.so; this module only orders the calls,
-moves the state between steps and keeps the statistics.
+The loop lives in libecodp.so (``dp_loop_create`` / ``dp_loop_step``): it
+solves the full route once, keeps one plan per horizon length for the whole
+drive and moves it along the route in place, and per step does the stop-line
+wait at a red signal (Eq. 5c, Eq. 8), the horizon's terminal table from the
+full-route values, the recorded solve, the FP64 rollout whose first step is
+the plant step (Eq. 1-2, 5a-b), and the speed-limit and red-crossing checks.
+This module marshals the route, times each step on the host clock and
+collects the rows.
 """
 from __future__ import annotations
 
+import ctypes as C
 import gc
-import math
 import statistics
 import time
 
+from . import _lib as L
 from . import instances as ins
-from .api import Plan, terminal_from_values
-
-
-def _red_wait(lights, stage, t_abs):
-    """Seconds until green for a vehicle stopped at the signal of ``stage``
-    (two-phase SPaT of Eq. 8: red iff (t - O) mod C < R); 0 when green or
-    when the stage has no signal."""
-    for (L, Cy, R, O) in lights:
-        if L == stage:
-            ph = (t_abs - O) % Cy
-            return R - ph if ph < R else 0.0
-    return 0.0
+from .api import _Desc
 
 
 class ClosedLoop:
@@ -49,46 +32,53 @@ class ClosedLoop:
 
     ``route`` is a full-route instance (``instances.mpc_route``); the horizon
     has ``horizon`` steps on the time grid [0, t_f] x n_t and shares the
-    route's speed and SoC grids.  ``plan_kw`` goes to every horizon ``Plan``.
+    route's speed and SoC grids.  ``plan_kw``: ``timing`` (sum the sweep
+    launch times with events instead of replaying recorded graphs),
+    ``kernel`` and ``sweep_tile`` for the horizon plans.
     """
 
     def __init__(self, route: dict, horizon: int = ins.MPC_HORIZON, t_f: float = ins.MPC_T_F,
                  n_t: int = ins.MPC_N_T, device: int = 0, plan_kw: dict | None = None):
         import torch
         self.torch = torch
+        self.lib = L.load()
         self.route = route
-        self.horizon, self.t_f, self.n_t = int(horizon), float(t_f), int(n_t)
-        self.device = device
-        self.plan_kw = dict(plan_kw or {})
-        t0 = time.perf_counter()
-        self.full = Plan([route], store_all=True, device=device)
-        self.full.solve()
-        self.J_full = self.full.values(0)          # device [N + 1, n_v, n_soc, n_t_route]
-        torch.cuda.synchronize(device)
-        self.offline_ms = (time.perf_counter() - t0) * 1e3
+        kw = dict(plan_kw or {})
+        o = L.DpOptions()
+        o.flags = L.DP_TIMING if kw.pop("timing", False) else 0
+        o.kernel = int(kw.pop("kernel", 0) or 0)
+        o.tile[0] = int(kw.pop("sweep_tile", 0) or 0)
+        if kw:
+            raise ValueError(f"unknown plan options {sorted(kw)}")
+        self._desc = _Desc(route)
+        torch.cuda.init()
+        h = C.c_void_p()
+        L.check(self.lib.dp_loop_create(C.byref(self._desc.d), int(horizon), float(t_f), int(n_t), C.byref(o),
+                                        int(device), C.byref(h)), "dp_loop_create")
+        self._h = h
+        self.offline_ms = self.totals().offline_ms
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.dp_loop_destroy(h)
+            self._h = None
+
+    def totals(self) -> L.DpLoopTotals:
+        t = L.DpLoopTotals()
+        L.check(self.lib.dp_loop_get_totals(self._h, C.byref(t)), "dp_loop_get_totals")
+        return t
 
     def run(self, steps: int | None = None) -> dict:
         """Drive ``steps`` stages (default: to the end of the route).  Returns
         per-step rows (stage, clock, state, V_0, u_0*, latency) and trip totals;
         ``status`` is 0, or DP_EINFEASIBLE (-4) when no admissible control
         exists or the state leaves the SoC grid."""
-        torch = self.torch
-        r = self.route
-        N_route = int(r["N"])
+        N_route = int(self.route["N"])
         steps = N_route if steps is None else min(int(steps), N_route)
-        t_f_route = float(r["t_grid"][1])
-        J_inf = float(r["konst"][13])
-        s_lo, s_hi = r["soc_grid"][0], r["soc_grid"][1]
-        s, t_abs, v, soc = 0, float(r["t0_abs"]), float(r["v0"]), float(r["soc0"])
-        fuel = cost = 0.0
-        wait_s = 0.0
-        violations = 0
         rows = []
-        status = 0
         evals = 0
-        sweep_ms, launches = 0.0, 0
-        timing = bool(self.plan_kw.get("timing"))
-        stream = torch.cuda.current_stream(self.device)
+        row = L.DpLoopRow()
         # a full garbage collection scans every object torch has created and
         # takes tens of milliseconds: the existing heap leaves the
         # collector's view for the loop, so a step pays only for its own objects
@@ -96,59 +86,30 @@ class ClosedLoop:
         gc.freeze()
         try:
             for _ in range(steps):
-                t_start = time.perf_counter()
-                if v == 0.0:
-                    tau = _red_wait(r["lights"], s, t_abs)
-                    t_abs += tau
-                    wait_s += tau
-                    cost += r["theta"][3] * tau
-                win = ins.mpc_window(r, s, t_abs, v, soc, self.horizon, self.t_f, self.n_t)
-                N = int(win["N"])
-                win["terminal_V"] = terminal_from_values(self.J_full[s + N], t_f_route, t_abs - float(r["t0_abs"]),
-                                                         self.n_t, self.t_f, J_inf)
-                stream.synchronize()                    # the plan copies the table at build
-                plan = Plan([win], device=self.device, **self.plan_kw)
-                V0, u0 = plan.solve()
-                traj, _ = plan.rollout()
-                # rows 0 and 1: the applied control and the plant step (the rollout's
-                # own status covers its whole open-loop horizon, of which only the
-                # first step is applied here)
-                head = traj[0][:2].cpu()
-                lat_ms = (time.perf_counter() - t_start) * 1e3
-                evals += ins.evaluations(win)
-                if timing:
-                    ms, n = plan.sweep_time()
-                    sweep_ms += ms
-                    launches += n
-                V0h = float(V0.cpu()[0])
-                u = int(head[0, 3])
-                rows.append({"s": s, "t_abs": t_abs, "v": v, "soc": soc, "V0": V0h, "u0": u, "latency_ms": lat_ms})
-                v1, soc1, dt = float(head[1, 0]), float(head[1, 1]), float(head[1, 2])
-                if u < 0 or not (math.isfinite(v1) and math.isfinite(soc1) and math.isfinite(dt)):
-                    status = -4                         # no admissible control from this state
+                if self.totals().stage >= N_route:
                     break
-                fuel += float(head[1, 6])
-                cost += float(head[1, 7])
-                s += 1
-                v, soc, t_abs = v1, soc1, t_abs + dt
-                if s < N_route:
-                    if v > float(r["vmax"][s]):
-                        violations += 1
-                    if v > 0.0 and _red_wait(r["lights"], s, t_abs) > 0.0:
-                        violations += 1                 # crossing a signal during red
-                if not (s_lo <= soc <= s_hi):
-                    status = -4
+                t0 = time.perf_counter()
+                L.check(self.lib.dp_loop_step(self._h, C.byref(row)), "dp_loop_step")
+                lat_ms = (time.perf_counter() - t0) * 1e3
+                evals += int(row.evaluations)
+                rows.append({"s": row.stage, "t_abs": row.t_abs, "v": row.v, "soc": row.soc, "V0": float(row.V0),
+                             "u0": int(row.u0), "latency_ms": lat_ms, "wait_s": row.wait_s,
+                             "violations": int(row.violations)})
+                if row.status != L.DP_OK:
                     break
         finally:
             gc.unfreeze()
+        t = self.totals()
         lat = [x["latency_ms"] for x in rows]
         return {
-            "steps": rows, "stage": s, "v": v, "soc": soc, "t_abs": t_abs,
-            "fuel_g": fuel, "cost": cost, "wait_s": wait_s, "violations": violations, "status": status,
+            "steps": rows, "stage": t.stage, "v": t.v, "soc": t.soc, "t_abs": t.t_abs,
+            "fuel_g": t.fuel_g, "cost": t.cost, "wait_s": t.wait_s, "violations": t.violations,
+            "status": t.status,
             "latency_ms": {"mean": statistics.mean(lat) if lat else None,
                            "var": statistics.pvariance(lat) if len(lat) > 1 else 0.0,
                            "max": max(lat) if lat else None,
                            "argmax_step": lat.index(max(lat)) if lat else None,
                            "median": statistics.median(lat) if lat else None},
-            "offline_ms": self.offline_ms, "evals": evals, "sweep_ms": sweep_ms, "sweep_launches": launches,
+            "offline_ms": self.offline_ms, "evals": evals, "sweep_ms": t.sweep_ms,
+            "sweep_launches": t.sweep_launches,
         }

@@ -112,6 +112,29 @@ def test_null_arguments(lib):
     a = C.c_size_t()
     assert lib.dp_workspace_size(None, C.byref(a), None, None) == L.DP_EINVAL
     lib.dp_destroy(None)
+    assert lib.dp_loop_create(None, 20, 80.0, 40, None, 0, C.byref(h)) == L.DP_EINVAL
+    assert lib.dp_loop_step(None, None) == L.DP_EINVAL
+    assert lib.dp_loop_get_totals(None, None) == L.DP_EINVAL
+    lib.dp_loop_destroy(None)
+
+
+@pytest.mark.parametrize("args,needle", [
+    ((0, 80.0, 40, 0), "horizon"),
+    ((20, 0.0, 40, 0), "time grid"),
+    ((20, 80.0, 1, 0), "time grid"),
+    ((20, 80.0, 40, L.DP_GRAPH), "DP_TIMING"),
+])
+def test_loop_validated_before_device(lib, args, needle):
+    """dp_loop_create rejects a bad horizon, time grid or option flag before
+    it touches a device."""
+    d = _Desc(ins.mpc_route(seed=9, length_m=600.0, n_lights=2))
+    horizon, t_f, n_t, flags = args
+    opt = L.DpOptions()
+    opt.flags = flags
+    h = C.c_void_p()
+    assert lib.dp_loop_create(C.byref(d.d), horizon, t_f, n_t, C.byref(opt), 0, C.byref(h)) == L.DP_EINVAL
+    assert needle in last_error(lib)
+    assert not h.value
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU device node is present")

@@ -161,3 +161,35 @@ def test_closed_loop_matches_oracle(torch):
         assert loop["fuel_g"] == pytest.approx(ref["fuel"], rel=1e-9)
     lat = loop["latency_ms"]
     say("latency ms mean %.3f max %.3f" % (lat["mean"], lat["max"]))
+
+
+def test_closed_loop_drives_to_route_end(torch):
+    """The library loop (dp_loop) over a whole 300 m route with a signal:
+    every horizon length 20 .. 1 of its kept plans is used (the window
+    shrinks over the last 19 stages), against the oracle's loop step by step
+    (V_0 within 1e-4, the same u_0* unless a root near tie, plant states within
+    1e-9); past the last stage dp_loop_step reports DP_ESTATE."""
+    import ctypes as C
+    from paper_2104_01284_amd import _lib as L
+    from paper_2104_01284_amd.mpc import ClosedLoop
+    route = ins.mpc_route(seed=5, length_m=300.0, n_lights=1)
+    loop = ClosedLoop(route)
+    res = loop.run()
+    say("route end: stage", res["stage"], "status", res["status"], "fuel", res["fuel_g"], "wait", res["wait_s"])
+    ref = oracle.closed_loop(route, int(route["N"]), ins.MPC_HORIZON, ins.MPC_T_F, ins.MPC_N_T, ins.mpc_window)
+    assert res["status"] == 0 and ref["status"] == 0
+    parted = False
+    for g, o in zip(res["steps"], ref["steps"]):
+        assert g["s"] == o["s"]
+        for key in ("v", "soc", "t_abs"):
+            assert abs(g[key] - o[key]) <= 1e-9 * max(1.0, abs(o[key])), (g["s"], key, g[key], o[key])
+        assert abs(g["V0"] - o["V0"]) <= 1e-4 * abs(o["V0"]), (g["s"], g["V0"], o["V0"])
+        if g["u0"] != o["u0"]:
+            assert o["q2"] - o["V0"] < 1e-4 * max(1.0, abs(o["V0"])), (g["s"], g["u0"], o["u0"])
+            parted = True
+            break
+    if not parted:
+        assert res["stage"] == int(route["N"]) and len(res["steps"]) == int(route["N"])
+        assert res["fuel_g"] == pytest.approx(ref["fuel"], rel=1e-9)
+        row = L.DpLoopRow()
+        assert loop.lib.dp_loop_step(loop._h, C.byref(row)) == L.DP_ESTATE
