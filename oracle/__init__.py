@@ -47,6 +47,7 @@ class OrInst(C.Structure):
         ("theta", C.c_double * 5), ("konst", C.c_double * 16), ("fuel", C.c_double * 6),
         ("terminal_V", C.POINTER(C.c_double)),
         ("wait_at_red", C.c_int32),
+        ("l_yel", C.POINTER(C.c_double)),
     ]
 
 
@@ -105,6 +106,8 @@ class Instance:
         self.l_cycle = np.array([x[1] for x in L], dtype=np.float64)
         self.l_red = np.array([x[2] for x in L], dtype=np.float64)
         self.l_off = np.array([x[3] for x in L], dtype=np.float64)
+        # an optional fifth entry: the yellow duration before red (Sec. III)
+        self.l_yel = np.array([x[4] if len(x) > 4 else 0.0 for x in L], dtype=np.float64)
         tv = inst.get("terminal_V")
         self.term = None if tv is None else np.ascontiguousarray(tv, dtype=np.float64).ravel()
         s = OrInst()
@@ -117,6 +120,7 @@ class Instance:
         s.l_cycle = _ptr(self.l_cycle, C.c_double)
         s.l_red = _ptr(self.l_red, C.c_double)
         s.l_off = _ptr(self.l_off, C.c_double)
+        s.l_yel = _ptr(self.l_yel, C.c_double)
         s.t0_abs, s.v0, s.soc0 = inst["t0_abs"], inst["v0"], inst["soc0"]
         s.v_lo, s.v_hi, s.n_v = inst["v_grid"]
         s.s_lo, s.s_hi, s.n_s = inst["soc_grid"]
@@ -303,13 +307,21 @@ def window_terminal(J_slab, t_f_src, t_shift, n_t, t_f, J_inf):
 
 
 def red_wait(inst_route, stage, t_abs):
-    """Wait of a vehicle stopped at the stop line of a red signal at ``stage``
-    until the end of red (Eq. 5c, Eq. 8); 0 if there is no signal or it is
-    green."""
-    for (L, Cy, R, O) in inst_route["lights"]:
+    """Wait of a vehicle stopped at the stop line of the signal at ``stage``
+    until green (Eq. 5c, Eq. 8): to the end of red, or in yellow (the optional
+    fifth light entry: its duration before red) to the end of the red that
+    follows, since a vehicle at rest is never inside its braking distance
+    after yellow began; 0 if there is no signal or it is green."""
+    for light in inst_route["lights"]:
+        L, Cy, R, O = light[:4]
+        Y = light[4] if len(light) > 4 else 0.0
         if L == stage:
             ph = (t_abs - O) % Cy
-            return R - ph if ph < R else 0.0
+            if ph < R:
+                return R - ph
+            if Y > 0.0 and ph >= Cy - Y and ph - (Cy - Y) > 0.0:
+                return (Cy - ph) + R
+            return 0.0
     return 0.0
 
 

@@ -242,13 +242,40 @@ static int light_at(const or_inst *I, int k)
     return -1;
 }
 
-/* Two-phase signal: red iff ((t_abs - offset) mod cycle) in [0, red). */
-static int is_red(const or_inst *I, int L, double t_rel, double *phase)
+/* Signal of stage L at relative time t_rel (Eq. 8, with the yellow phase of
+ * Sec. III).  Phase x = (t_abs - offset) mod cycle: red for x in [0, R),
+ * yellow for x in [C - Y, C) (the Y seconds before red), green otherwise.
+ * Yellow counts as green when the vehicle, crossing at speed v, was within
+ * its critical braking distance v^2 / (2 b) of the stop line when yellow
+ * began (b = -a_min, the braking limit), i.e. when the time since yellow
+ * began is at most v / (2 b); otherwise it has to stop, as in red.  Returns 1
+ * when the vehicle has to stop, with *tau the time until green; *phase = x. */
+static int must_stop(const or_inst *I, int L, double t_rel, double v, double *tau, double *phase)
 {
-    double x = fmod(I->t0_abs + t_rel - I->l_off[L], I->l_cycle[L]);
-    if (x < 0.0) x += I->l_cycle[L];
+    const double C = I->l_cycle[L], R = I->l_red[L], Y = I->l_yel ? I->l_yel[L] : 0.0;
+    double x = fmod(I->t0_abs + t_rel - I->l_off[L], C);
+    if (x < 0.0) x += C;
     *phase = x;
-    return x < I->l_red[L];
+    *tau = 0.0;
+    if (x < R) {
+        *tau = R - x;
+        return 1;
+    }
+    if (Y > 0.0 && x >= C - Y) {
+        const double since = x - (C - Y);
+        if (since > v / (2.0 * -I->konst[K_AMIN])) {
+            *tau = (C - x) + R;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+/* 1 when x (a phase from must_stop) lies in the yellow of signal L. */
+static int in_yellow(const or_inst *I, int L, double x)
+{
+    const double C = I->l_cycle[L], R = I->l_red[L], Y = I->l_yel ? I->l_yel[L] : 0.0;
+    return !(x < R) && Y > 0.0 && x >= C - Y;
 }
 
 /* --------------------------------------------------------- one node, one u -- */
@@ -317,9 +344,8 @@ double or_node_q(const or_inst *I, int k, const double *Jn, int i, int j, int m,
     double xi = grid_val(I->s_lo, I->s_hi, I->n_s, j);
     if (u == -2) {
         int L = light_at(I, k);
-        double phase;
-        if (L < 0 || !is_red(I, L, grid_val(0.0, I->t_f, I->n_t, m), &phase)) return Jinf;
-        double tau = I->l_red[L] - phase;
+        double phase, tau;
+        if (L < 0 || !must_stop(I, L, grid_val(0.0, I->t_f, I->n_t, m), 0.0, &tau, &phase)) return Jinf;
         cf_t t = cf_shift(m, tau / h.ht, I->n_t);
         if (!cf_in_range(t, I->n_t)) return Jinf;
         cf_t cv = cf_of((double)i, I->n_v), cs = cf_of((double)j, I->n_s);
@@ -345,8 +371,8 @@ void or_node(const or_inst *I, int k, const double *Jn, int i, int j, int m,
     const double v = grid_val(I->v_lo, I->v_hi, I->n_v, i);
     double best = Jinf, second = Jinf;
     int bu = -1;
-    double phase = 0.0;
-    int red = L >= 0 && is_red(I, L, grid_val(0.0, I->t_f, I->n_t, m), &phase);
+    double phase = 0.0, tau = 0.0;
+    int red = L >= 0 && must_stop(I, L, grid_val(0.0, I->t_f, I->n_t, m), v, &tau, &phase);
     if (v > I->vmax[k]) {
         /* infeasible node */
     } else if (red) {
@@ -430,13 +456,12 @@ void or_stage(const or_inst *I, int k, const double *Jn, double *Jk, int16_t *pi
                 double best = Jinf, second = Jinf;
                 int bu = -1;
                 int red = 0;
-                double phase = 0.0;
-                if (L >= 0) red = is_red(I, L, grid_val(0.0, I->t_f, nt, m), &phase);
+                double phase = 0.0, tau = 0.0;
+                if (L >= 0) red = must_stop(I, L, grid_val(0.0, I->t_f, nt, m), v, &tau, &phase);
                 if (speed_bad) {
                     /* infeasible node */
                 } else if (red) {
                     if (v == 0.0 && I->wait_at_red) {
-                        double tau = I->l_red[L] - phase;
                         cf_t t = cf_shift(m, tau / h.ht, nt);
                         if (cf_in_range(t, nt)) {
                             double val = wt * tau + interp_cf(I, Jn, cf_of((double)i, nv), cf_of((double)j, ns), t);
@@ -565,16 +590,16 @@ int or_rollout(const or_inst *I, const int16_t *pi_all, int32_t u0, double *traj
             if (v > I->vmax[0]) (*viol)++;
         } else {
             int L = light_at(I, k);
-            double phase;
-            if (L >= 0 && is_red(I, L, t, &phase)) {
+            double phase, tau;
+            if (L >= 0 && must_stop(I, L, t, v, &tau, &phase)) {
                 if (v == 0.0 && I->wait_at_red) {
-                    double tau = I->l_red[L] - phase;   /* Eq. 5c: wait for the red-green switch */
+                    /* Eq. 5c: wait for green */
                     row[3] = -2.0;
                     t += tau;
                     cost += wt * tau;
                     continue;
                 }
-                (*viol)++;                               /* crossing in red */
+                (*viol)++;       /* crossing when it has to stop (red, or yellow past the braking distance) */
             }
             if (v > I->vmax[k]) (*viol)++;
             int oog = 0;
@@ -694,9 +719,8 @@ void or_tangent(const or_inst *I, const double *J_all, const int16_t *pi_all, in
                 const int u = pik[n];
                 for (int q = 0; q < 5; q++) Dk[q * S + n] = 0.0;
                 if (u == -2) {
-                    double phase;
-                    is_red(I, L, grid_val(0.0, I->t_f, nt, m), &phase);
-                    double tau = I->l_red[L] - phase;
+                    double phase, tau;
+                    must_stop(I, L, grid_val(0.0, I->t_f, nt, m), 0.0, &tau, &phase);
                     cf_t t = cf_shift(m, tau / h.ht, nt);
                     cf_t cv = cf_of((double)i, nv), cs = cf_of((double)j, ns);
                     for (int q = 0; q < 5; q++)
@@ -821,9 +845,8 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
                     if (rho_sum) rho_sum[k] += r;
                     const int u = pik[n];
                     if (u == -2) {
-                        double phase;
-                        is_red(I, L, grid_val(0.0, I->t_f, nt, m), &phase);
-                        double tau = I->l_red[L] - phase;
+                        double phase, tau;
+                        must_stop(I, L, grid_val(0.0, I->t_f, nt, m), 0.0, &tau, &phase);
                         cf_t t = cf_shift(m, tau / h.ht, nt);
                         g[T_WT] += r * tau;
                         etime += r * tau;
@@ -831,10 +854,12 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
                         if (dspat) {
                             /* signal timing (Eq. 5c, Eq. 8): the wait value
                              * w_t tau + J_{k+1}(t_m + tau) moves with tau =
-                             * R - phase, and phase = t - O - n C (n whole
+                             * R - phase in red and tau = C - phase + R in
+                             * yellow, and phase = t - O - n C (n whole
                              * cycles), so dtau/dO = dtau/dR = 1 and dtau/dC =
-                             * n.  The red masks are constant between switching
-                             * instants: their derivative is zero. */
+                             * n (red) or n + 1 (yellow).  The red and yellow
+                             * masks are constant between switching instants:
+                             * their derivative is zero. */
                             double gJ[3];
                             interp_grad(I, Jn, cf_of((double)i, nv), cf_of((double)j, ns), t, gJ);
                             const double dval = wt + gJ[2] / h.ht;
@@ -842,7 +867,7 @@ void or_adjoint(const or_inst *I, const double *J_all, const int16_t *pi_all, in
                             const double ncyc = nearbyint((t_abs - I->l_off[L] - phase) / I->l_cycle[L]);
                             dspat[3 * L + 0] += r * dval;
                             dspat[3 * L + 1] += r * dval;
-                            dspat[3 * L + 2] += r * dval * ncyc;
+                            dspat[3 * L + 2] += r * dval * (ncyc + (in_yellow(I, L, phase) ? 1.0 : 0.0));
                         }
                         scatter(I, rn, r, cf_of((double)i, nv), cf_of((double)j, ns), t);
                     } else if (u >= 0) {

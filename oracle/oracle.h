@@ -48,6 +48,7 @@ typedef struct {
     double fuel[6];         /* q0..q5 */
     const double *terminal_V; /* optional [n_v*n_s*n_t] terminal table, NULL = none */
     int32_t wait_at_red;    /* 1: a stopped vehicle waits out a red phase (Eq. 5c) */
+    const double *l_yel;    /* [n_lights] yellow duration Y before red (0 = two phases), or NULL */
 } or_inst;
 
 /* Continuous one-step model.  out[] = {v1, dt, cost, acc, P_bat, I_bat, mfuel, q}.

@@ -305,6 +305,26 @@ def with_torque_limits(inst: dict, p_eng: float, p_bsg: float) -> dict:
     return out
 
 
+def with_yellow(inst: dict, yellow: float) -> dict:
+    """The instance with a yellow phase of ``yellow`` seconds before every
+    red (three-phase signals, Sec. III): a light becomes (stage, C, R, O, Y),
+    yellow for (t_abs - O) mod C in [C - Y, C)."""
+    out = copy.deepcopy(inst)
+    lights = []
+    for light in out["lights"]:
+        L, C, R, O = light[:4]
+        if not 0.0 <= yellow <= C - R:
+            raise ValueError("the yellow phase must fit between green and red")
+        lights.append((L, C, R, O, float(yellow)))
+    out["lights"] = lights
+    return out
+
+
+def plain_yellow(seed: int = 1) -> dict:
+    """The 500 m instance with an 8 s yellow before the signal's red."""
+    return with_yellow(plain(seed), 8.0)
+
+
 def with_stop_signs(inst: dict, stages) -> dict:
     """The instance with stop signs at the given stages: the route speed
     limit there is 0 (Eq. 7a), so the vehicle must be at rest at the sign."""

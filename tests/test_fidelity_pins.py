@@ -62,3 +62,68 @@ def test_stop_sign_forces_rest():
     # the sign costs time: the unconstrained instance is at least as cheap
     free = oracle.solve(ins.plain())
     assert free["V0"] <= r["V0"]
+
+
+def test_yellow_rule_closed_form():
+    """Three-phase signal (Sec. III): at the signal stage a node in yellow
+    (phase x in [C - Y, C)) must stop, as in red, exactly when the time since
+    yellow began exceeds v / (2 b), b = -a_min: the vehicle was farther from
+    the stop line than its critical braking distance v^2 / (2 b) when yellow
+    began; otherwise yellow is green and the node keeps the two-phase value.
+    A vehicle at rest in yellow waits until green, C - x + R, its value w_t tau
+    plus the next stage lerped at t_m + tau.  Red nodes and every other stage
+    are unchanged; a zero yellow reproduces the two-phase solve exactly."""
+    import math
+    base = ins.plain()
+    inst = ins.with_yellow(base, 8.0)
+    r0 = oracle.solve(base)
+    r = oracle.solve(inst)
+    k, C, R, O, Y = inst["lights"][0]
+    b = -inst["konst"][10]
+    Jinf = inst["konst"][13]
+    wt = inst["theta"][3]
+    v = np.linspace(*inst["v_grid"][:2], inst["v_grid"][2])
+    t = np.linspace(*inst["t_grid"][:2], inst["t_grid"][2])
+    ht = t[1] - t[0]
+    nt = len(t)
+    assert np.array_equal(r["J"][k + 1:], r0["J"][k + 1:])
+    blocked = green = 0
+    for m in range(nt):
+        x = (inst["t0_abs"] + t[m] - O) % C
+        if x < R or x < C - Y:
+            assert np.array_equal(r["J"][k, :, :, m], r0["J"][k, :, :, m]), m
+            continue
+        since = x - (C - Y)
+        for i in range(len(v)):
+            if v[i] > 0.0 and since > v[i] / (2.0 * b):
+                blocked += 1
+                assert np.all(r["J"][k, i, :, m] == Jinf) and np.all(r["pi"][k, i, :, m] == -1), (m, i)
+            elif v[i] > 0.0:
+                green += 1
+                assert np.array_equal(r["J"][k, i, :, m], r0["J"][k, i, :, m]), (m, i)
+            else:
+                tau = (C - x) + R
+                rt = m + tau / ht
+                for j in range(inst["soc_grid"][2]):
+                    if rt > nt - 1:
+                        assert r["J"][k, 0, j, m] == Jinf
+                        continue
+                    c = min(int(math.floor(rt)), nt - 2)
+                    f = rt - c
+                    want = wt * tau + (1 - f) * r["J"][k + 1, 0, j, c] + f * r["J"][k + 1, 0, j, c + 1]
+                    assert r["J"][k, 0, j, m] == min(want, Jinf) or abs(r["J"][k, 0, j, m] - want) <= 1e-12 * want
+    assert blocked > 20 and green > 20
+    same = oracle.solve(ins.with_yellow(base, 0.0))
+    assert np.array_equal(same["J"], r0["J"]) and np.array_equal(same["pi"], r0["pi"])
+
+
+def test_red_wait_in_yellow():
+    """The closed loop's stop-line wait: to the end of red in red; in yellow,
+    for a vehicle at rest, to the end of the red that follows."""
+    inst = ins.with_yellow(ins.plain(), 8.0)
+    k, C, R, O, Y = inst["lights"][0]
+    assert oracle.red_wait(inst, k, O + 5.0) == R - 5.0          # red
+    assert oracle.red_wait(inst, k, O + 30.0) == 0.0              # green
+    x = C - Y + 3.0                                              # 3 s into yellow
+    assert oracle.red_wait(inst, k, O + x) == (C - x) + R
+    assert oracle.red_wait(inst, k, O + C - Y) == 0.0             # the instant yellow begins

@@ -3,7 +3,8 @@
 Every case below edits one expression of ``oracle/oracle.c`` (a plausible
 slip: a sign, a dropped term, a transposed operand, a wrong comparison),
 builds that copy into a separate library on the CPU and runs the named pins
-of ``tests/test_oracle_pins.py`` against it; at least one of them must fail.
+of ``tests/test_oracle_pins.py`` (and ``tests/test_fidelity_pins.py``) against
+it; at least one of them must fail.
 The oracle in the repository is not touched.
 """
 import contextlib
@@ -13,6 +14,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_fidelity_pins as fpins
 import test_oracle_pins as pins
 from paper_2104_01284_amd import instances as ins
 
@@ -39,12 +41,9 @@ MUTANTS = [
     ("tie-break", "if (Q < best) { second = best; best = Q; bu = u; }\n                        else",
      "if (Q <= best) { second = best; best = Q; bu = u; }\n                        else",
      [pins.test_tie_break_lowest_control_index]),
-    ("wait time", "double tau = I->l_red[L] - phase;\n                        cf_t t = cf_shift(m, tau / h.ht, nt);\n"
-     "                        if (cf_in_range(t, nt)) {",
-     "double tau = phase;\n                        cf_t t = cf_shift(m, tau / h.ht, nt);\n"
-     "                        if (cf_in_range(t, nt)) {",
+    ("wait time", "*tau = R - x;", "*tau = x;",
      [pins.test_red_phase_invariant_and_wait]),
-    ("half-open red", "return x < I->l_red[L];", "return x <= I->l_red[L];",
+    ("half-open red", "if (x < R) {", "if (x <= R) {",
      [pins.test_red_phase_half_open]),
     ("fuel coefficient", "q[4] * v * Te", "q[4] * Te",
      [pins.test_fuel_map_monomials]),
@@ -60,6 +59,10 @@ MUTANTS = [
      [pins.test_markov_policy_bruteforce, pins.test_openloop_bruteforce_refinement]),
     ("rollout tie rule", "if (w > bw || (w == bw && nidx < bn))", "if (w >= bw)",
      [pins.test_rollout_policy_lookup_nearest_corner]),
+    ("yellow braking time", "if (since > v / (2.0 * -I->konst[K_AMIN])) {", "if (since > v / (-I->konst[K_AMIN])) {",
+     [fpins.test_yellow_rule_closed_form]),
+    ("yellow wait", "*tau = (C - x) + R;", "*tau = (C - x);",
+     [fpins.test_yellow_rule_closed_form]),
 ]
 
 
