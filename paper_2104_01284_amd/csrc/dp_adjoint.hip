@@ -209,6 +209,12 @@ __device__ void step_partials(const DevInst &P, double v, const PT &p, double I,
 __device__ void interp_grad(const DevInst &P, const float *J, const Cells &x, double g[3])
 {
 #pragma clang fp contract(off)
+    // the eight corners, loaded once (cells are at most n - 2 on every axis)
+    double Jv[8];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int e = 0; e < 2; e++)
+                Jv[(a * 2 + b) * 2 + e] = (double)J[((long)(x.c[0] + a) * P.n_s + (x.c[1] + b)) * P.n_t + (x.c[2] + e)];
     for (int d = 0; d < 3; d++) {
         g[d] = 0.0;
         if (!(x.f[d] > 0.0 && x.f[d] < 1.0)) continue;
@@ -229,9 +235,7 @@ __device__ void interp_grad(const DevInst &P, const float *J, const Cells &x, do
                         w *= wo;
                     }
                     if (skip) continue;
-                    const double Jc =
-                        (double)J[((long)(x.c[0] + a) * P.n_s + (x.c[1] + b)) * P.n_t + (x.c[2] + e)];
-                    acc += (bits[d] ? 1.0 : -1.0) * w * Jc;
+                    acc += (bits[d] ? 1.0 : -1.0) * w * Jv[(a * 2 + b) * 2 + e];
                 }
         g[d] = acc;
     }
@@ -521,14 +525,30 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
         }
         __syncthreads();
         const int na = s_cnt;
-        for (int a = threadIdx.x; a < na; a += blockDim.x) {
-            const long n = c0 + s_list[a];
-            const double r = s_rho[a];
-            const int m = (int)(n % P.n_t);
-            const long ij = n / P.n_t;
+        // Waves walk the list together (every lane takes part in the
+        // exchanges below, past the list's end too).  Occupied nodes come in
+        // node order within a wave's share, so neighbouring lanes often hold
+        // nodes m - 1 and m of one (speed, SoC) row under the same control:
+        // their successors then share speed and SoC cells and weights and sit
+        // one time cell apart, and the upper time corners of the first are the
+        // lower corners of the second.  The second lane adds the first's four
+        // upper terms into its own four lower atomics and the first skips
+        // them: one add per shared cell instead of two.
+        for (int a0 = 0; a0 < na; a0 += blockDim.x) {
+            const int a = a0 + (int)threadIdx.x;
+            const bool live = a < na;
+            const int jj = live ? s_list[a] : -2;
+            const long n = c0 + jj;
+            const double r = live ? s_rho[a] : 0.0;
+            const int m = live ? (int)(n % P.n_t) : 0;
+            const long ij = live ? n / P.n_t : 0;
             const int j = (int)(ij % P.n_s);
             const int i = (int)(ij / P.n_s);
-            const int u = pik[n];
+            const int u = live ? (int)pik[n] : -1;
+            bool scat = false;     // a regular successor whose 8 corners this lane scatters
+            Cells x;
+            x.c[0] = x.c[1] = x.c[2] = 0;
+            x.f[0] = x.f[1] = x.f[2] = 0.0;
             if (u == -2) {
                 const TLEntry e = tl[m];
                 g[3] += r * e.tau;
@@ -550,32 +570,65 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
                 // the successor exactly as successor_cells forms it, the
                 // (i, u) terms from the stage table
                 const AdjEntry &e = tab[(long)i * P.n_u + u];
-                if (!e.ok) continue;
                 const double xi = P.s_lo + j * P.hs;
-                double I;
-                if (!battery_current(P, e.Pb, xi, I)) continue;
-                const double rs = (double)j - (e.dt * I) / (P.Cnom * P.hs);
-                if (!(rs >= 0.0 && rs <= P.n_s - 1)) continue;
-                Cells x;
-                x.c[0] = e.cv;
-                x.f[0] = e.fv;
-                cell_of(rs, P.n_s, x.c[1], x.f[1]);
-                int tc = m + e.dtc;
-                double ft = e.ft;
-                if (tc > P.n_t - 2) {
-                    ft += (double)(tc - (P.n_t - 2));
-                    tc = P.n_t - 2;
-                    if (ft > 1.0) continue;
+                double I = 0.0;
+                double rs = -1.0;
+                if (e.ok && battery_current(P, e.Pb, xi, I)) rs = (double)j - (e.dt * I) / (P.Cnom * P.hs);
+                if (rs >= 0.0 && rs <= P.n_s - 1) {
+                    x.c[0] = e.cv;
+                    x.f[0] = e.fv;
+                    cell_of(rs, P.n_s, x.c[1], x.f[1]);
+                    int tc = m + e.dtc;
+                    double ft = e.ft;
+                    if (tc > P.n_t - 2) {
+                        ft += (double)(tc - (P.n_t - 2));
+                        tc = P.n_t - 2;
+                    }
+                    x.c[2] = tc;
+                    x.f[2] = ft;
+                    if (ft <= 1.0) {
+                        scat = true;
+                        double gJ[3];
+                        interp_grad(P, Jn, x, gJ);
+                        const double sI = -(I / (P.Cnom * P.hs));
+                        for (int q = 0; q < 3; q++)
+                            g[q] += r * (e.dc[q] + e.drv[q] * gJ[0] + (sI * e.ddt[q]) * gJ[1] + e.drt[q] * gJ[2]);
+                        g[3] += r * e.dt;
+                    }
                 }
-                x.c[2] = tc;
-                x.f[2] = ft;
-                double gJ[3];
-                interp_grad(P, Jn, x, gJ);
-                const double sI = -(I / (P.Cnom * P.hs));
-                for (int q = 0; q < 3; q++)
-                    g[q] += r * (e.dc[q] + e.drv[q] * gJ[0] + (sI * e.ddt[q]) * gJ[1] + e.drt[q] * gJ[2]);
-                g[3] += r * e.dt;
-                scatter(P, rho_next, r, x, true);
+            }
+            // this lane's upper time corners (speed corner a, SoC corner b)
+            double up[4];
+            for (int q = 0; q < 4; q++) {
+                const int ca = q >> 1, cb = q & 1;
+                const double wa = ca ? x.f[0] : 1.0 - x.f[0];
+                const double wb = cb ? x.f[1] : 1.0 - x.f[1];
+                up[q] = scat && wa > 0.0 && wb > 0.0 && x.f[2] > 0.0 ? r * wa * wb * x.f[2] : 0.0;
+            }
+            // does the previous lane hold node n - 1 of this row under the same
+            // control, with its successor one time cell below this one's at the
+            // same time fraction (then all other weights agree as well)?
+            const int p_jj = __shfl_up(jj, 1);
+            const int p_u = __shfl_up(u, 1);
+            const int p_tc = __shfl_up(x.c[2], 1);
+            const double p_ft = __shfl_up(x.f[2], 1);
+            const int p_scat = __shfl_up((int)scat, 1);
+            double p_up[4];
+            for (int q = 0; q < 4; q++) p_up[q] = __shfl_up(up[q], 1);
+            const bool merge = scat && lane > 0 && p_scat && m > 0 && p_jj == jj - 1 && p_u == u &&
+                               p_tc == x.c[2] - 1 && p_ft == x.f[2];
+            const bool absorbed = __shfl_down((int)merge, 1) && lane < 63;
+            if (scat) {
+                for (int q = 0; q < 4; q++) {
+                    const int ca = q >> 1, cb = q & 1;
+                    const double wa = ca ? x.f[0] : 1.0 - x.f[0];
+                    const double wb = cb ? x.f[1] : 1.0 - x.f[1];
+                    double *dst = rho_next + ((long)(x.c[0] + ca) * P.n_s + (x.c[1] + cb)) * P.n_t + x.c[2];
+                    double lo = wa > 0.0 && wb > 0.0 && 1.0 - x.f[2] > 0.0 ? r * wa * wb * (1.0 - x.f[2]) : 0.0;
+                    if (merge) lo += p_up[q];
+                    if (lo > 0.0) unsafeAtomicAdd(dst, lo);
+                    if (!absorbed && up[q] > 0.0) unsafeAtomicAdd(dst + 1, up[q]);
+                }
             }
         }
         __syncthreads();   // the list is read before the next chunk rewrites it

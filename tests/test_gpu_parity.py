@@ -497,3 +497,55 @@ def test_signal_timing_sensitivities_edge_cases(torch):
     assert np.all(np.isnan(g5b.cpu().numpy()))
     with pytest.raises(DPError):
         Plan([t]).adjoint_spat()
+
+
+def test_adjoint_central_differences_on_gpu(torch):
+    """dp_adjoint on the 500 m instance against central differences of the
+    GPU's own V_0 at policy-stable points.  For each theta_p the step h starts
+    at 1e-2 |theta_p| and shrinks (3e-3, 1e-3) until, on the oracle's
+    occupancy support (the nodes the adjoint weights), the GPU policies at
+    theta +- h equal the one at theta wherever the oracle's FP64 gap between
+    the best and second-best candidate is at least 1e-4 max(1, |J|) (choices
+    inside that band are ties at FP32 resolution and may flip with any
+    perturbation), and u_0* is unchanged; the difference quotient must then
+    match the adjoint within the FP32 bound on V_0 (2e-6 |V_0| at each end, so
+    2e-6 |V_0| / h on the quotient) plus 1e-2 |dV/dtheta_p| for the step's
+    curvature and the near-tie flips.  At least four of the five parameters
+    must reach a stable step; the FP64 oracle's own 1e-4 differences are pinned
+    on the CPU."""
+    inst = ins.plain()
+    r = oracle.solve(inst, q2=True)
+    ad = oracle.adjoint(inst, r["J"], r["pi"], r["u0"], want_rho=True)
+    gap = r["q2"] - r["J"][:-1]
+    firm = (ad["rho"][:-1] > 0) & (gap >= 1e-4 * np.maximum(1.0, np.abs(r["J"][:-1])))
+    firm = torch.from_numpy(firm).cuda()
+    say("support nodes", int((ad["rho"][:-1] > 0).sum()), "firm", int(firm.sum()))
+    base = Plan([inst], store_all=True)
+    V0, u0 = base.solve()
+    torch.cuda.synchronize()
+    g = base.adjoint()[0].cpu().numpy()
+    pi0 = base.policy(0)
+    V0f = float(V0[0])
+    checked = 0
+    for p in range(5):
+        th = list(inst["theta"])
+        for rel in (1e-2, 3e-3, 1e-3):
+            h = rel * abs(th[p])
+            out = []
+            for sgn in (1.0, -1.0):
+                t = list(th)
+                t[p] += sgn * h
+                pl = Plan([ins.with_theta(inst, t)], store_all=True)
+                Vx, ux = pl.solve()
+                torch.cuda.synchronize()
+                moved = int((pl.policy(0)[firm] != pi0[firm]).sum())
+                out.append((float(Vx[0]), int(ux[0]) == int(u0[0]) and moved == 0, moved))
+                del pl
+            fd = (out[0][0] - out[1][0]) / (2.0 * h)
+            say("theta", p, "rel", rel, "fd", fd, "adjoint", g[p], "firm nodes moved", out[0][2], out[1][2])
+            if out[0][1] and out[1][1]:
+                tol = 2e-6 * abs(V0f) / h + 1e-2 * abs(g[p])
+                assert abs(fd - g[p]) <= tol, (p, rel, fd, g[p], tol)
+                checked += 1
+                break
+    assert checked >= 4
