@@ -236,12 +236,11 @@ def main():
     opts = dict(sweep_tile=args.tile, split=args.split, wg_per_cu=args.wg_per_cu, kernel=args.kernel,
                 rounds=args.rounds)
     tuned = None
-    # a batch keeps the library's per-instance choice: the tuner times shapes
-    # alone, while in a batch they share the GPU with the other instances
-    if not args.no_tune and not (args.kernel or args.tile) and not batched:
-        from paper_2104_01284_amd.autotune import tuned_options
+    if not args.no_tune and not (args.kernel or args.tile):
+        from paper_2104_01284_amd.autotune import tuned_batch_options, tuned_options
         t0 = time.perf_counter()
-        tuned = tuned_options(insts, verbose=True)
+        # a batch: one SoC tile for all, by whole-batch solves
+        tuned = tuned_batch_options(insts, verbose=True) if batched else tuned_options(insts, verbose=True)
         print(f"[bench] sweep autotune {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         opts["inst_opts"] = tuned
     if batched:

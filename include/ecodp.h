@@ -106,6 +106,12 @@ typedef struct {
     const float *terminal_V;   /* optional [n_v][n_soc][n_t] added to the terminal cost; NULL = none
                                   (host memory, or device memory with DP_TERMINAL_DEVICE)          */
     uint32_t flags;            /* DP_WAIT_AT_RED, DP_TERMINAL_DEVICE */
+    const double *light_yellow;/* [n_lights] yellow duration Y >= 0 before red, Y + R <= C: yellow iff
+                                  (t_abs - O) mod C in [C - Y, C) (three-phase signals, Sec. III), or
+                                  NULL = none.  A vehicle crossing at speed v in yellow must stop, as
+                                  in red, when the time since yellow began exceeds v / (2 b), b =
+                                  -a_min (it was beyond its critical braking distance v^2 / (2 b)
+                                  when yellow began); else yellow counts as green.  Needs a_min < 0. */
 } dp_problem_desc;
 
 typedef struct {

@@ -44,6 +44,7 @@ class DpProblemDesc(C.Structure):
         ("theta", C.c_double * 5), ("konst", C.c_double * 16), ("fuel", C.c_double * 6),
         ("terminal_V", C.POINTER(C.c_float)),
         ("flags", C.c_uint32),
+        ("light_yellow", C.POINTER(C.c_double)),
     ]
 
 

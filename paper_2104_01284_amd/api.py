@@ -30,6 +30,8 @@ class _Desc:
         self.lc = np.array([x[1] for x in lights], dtype=np.float64)
         self.lr = np.array([x[2] for x in lights], dtype=np.float64)
         self.lo = np.array([x[3] for x in lights], dtype=np.float64)
+        # an optional fifth entry: the yellow duration before red (three-phase signals)
+        self.ly = np.array([x[4] if len(x) > 4 else 0.0 for x in lights], dtype=np.float64)
         tv = inst.get("terminal_V")
         self.term_dev = None
         self.term = None
@@ -51,6 +53,7 @@ class _Desc:
         d.light_cycle = _dptr(self.lc)
         d.light_red = _dptr(self.lr)
         d.light_offset = _dptr(self.lo)
+        d.light_yellow = _dptr(self.ly) if any(len(x) > 4 for x in lights) else None
         d.t0_abs, d.v0, d.soc0 = inst["t0_abs"], inst["v0"], inst["soc0"]
         d.v_lo, d.v_hi, d.n_v = inst["v_grid"]
         d.soc_lo, d.soc_hi, d.n_soc = inst["soc_grid"]

@@ -123,3 +123,67 @@ def tuned_options(instances, device: int = 0, cache_path: str | None = None, ver
         except OSError:
             pass
     return out
+
+
+# SoC tiles a batch is timed with (one tile for every instance, so that the
+# persistent sweep runs one kernel class per workgroup size)
+BATCH_TILES = (8, 4)
+
+
+def batch_key(instances, device_name: str) -> str:
+    import hashlib
+    shapes = "|".join(shape_key(inst, "") for inst in instances)
+    return f"{device_name}|batch{len(instances)}|{hashlib.sha256(shapes.encode()).hexdigest()[:16]}"
+
+
+def tune_batch(instances, device: int = 0, tiles=BATCH_TILES, repeats: int = 1) -> dict:
+    """Whole solves of the batch with every instance on one SoC tile (after
+    one untimed solve each); returns the fastest as {"tile", "ms", "all"}."""
+    import torch
+    from .api import Plan
+    results = {}
+    for t in tiles:
+        plan = Plan(instances, sweep_tile=t, device=device)
+        plan.solve()
+        torch.cuda.synchronize(device)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(repeats):
+            plan.solve()
+        b.record()
+        torch.cuda.synchronize(device)
+        results[str(t)] = a.elapsed_time(b) / repeats
+        del plan
+        torch.cuda.empty_cache()
+    best = min(results, key=results.get)
+    return {"tile": int(best), "ms": results[best], "all": results}
+
+
+def tuned_batch_options(instances, device: int = 0, cache_path: str | None = None, verbose: bool = False):
+    """Per-instance options of a batch: the SoC tile whose whole-batch solve
+    was fastest (timed once per (device, batch of shapes), then cached)."""
+    import torch
+    path = cache_path or default_cache_path()
+    cache = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    key = batch_key(instances, torch.cuda.get_device_name(device))
+    if key not in cache:
+        cache[key] = tune_batch(instances, device)
+        if verbose:
+            print(f"[autotune] {key}: {cache[key]}", file=sys.stderr, flush=True)
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        except OSError:
+            pass
+    tile = int(cache[key]["tile"])
+    return [(0, tile, 0, 0)] * len(instances)

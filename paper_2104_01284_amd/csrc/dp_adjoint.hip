@@ -5,13 +5,26 @@
 
 namespace ecodp {
 
-__device__ inline bool red_at(const DevInst &P, int L, double t_rel, double &phase)
+// 1 when a vehicle at speed v has to stop at signal L at relative time t_rel
+// (Eq. 8, with the yellow rule of Sec. III: red, or yellow once more time has
+// passed since yellow began than v / (2 b), b = -a_min), with tau the time
+// until green.
+__device__ inline bool must_stop(const DevInst &P, int L, double t_rel, double v, double &tau)
 {
 #pragma clang fp contract(off)
-    double x = fmod(P.t0_abs + t_rel - P.l_off[L], P.l_cycle[L]);
-    if (x < 0.0) x += P.l_cycle[L];
-    phase = x;
-    return x < P.l_red[L];
+    const double C = P.l_cycle[L], R = P.l_red[L], Y = P.l_yel[L];
+    double x = fmod(P.t0_abs + t_rel - P.l_off[L], C);
+    if (x < 0.0) x += C;
+    tau = 0.0;
+    if (x < R) {
+        tau = R - x;
+        return true;
+    }
+    if (Y > 0.0 && x >= C - Y && x - (C - Y) > v / (2.0 * -P.amin)) {
+        tau = (C - x) + R;
+        return true;
+    }
+    return false;
 }
 
 // Control at an off-grid state: among the bracketing nodes with positive
@@ -101,10 +114,9 @@ __device__ void rollout_one(const DevInst &P, const int16_t *__restrict__ pi, co
             if (v > P.vmax[0]) viol++;
         } else {
             const int L = P.light_of_stage[k];
-            double phase;
-            if (L >= 0 && red_at(P, L, t, phase)) {
+            double tau;
+            if (L >= 0 && must_stop(P, L, t, v, tau)) {
                 if (v == 0.0 && P.wait) {
-                    const double tau = P.l_red[L] - phase;
                     row[3] = -2.0;
                     t += tau;
                     cost += P.wt * tau;

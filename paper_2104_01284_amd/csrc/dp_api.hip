@@ -67,7 +67,7 @@ struct Inst {
     size_t tl_dev_off = 0;     // offset (entries) of this instance's TL table in the plan's TL array
     int64_t evals = 0;
     std::vector<int> job_of_k; // grouped sweep: index of the (instance, k) job in the plan's job table
-    std::vector<double> l_cycle, l_red, l_off;   // signals, kept for dp_set_state
+    std::vector<double> l_cycle, l_red, l_off, l_yel;   // signals, kept for dp_set_state
     std::vector<char> same_tables;               // [k]: stage k's tables equal stage k+1's
 };
 
@@ -200,6 +200,13 @@ int validate(const dp_problem_desc &d, int b)
         if (!(finite(d.light_red[L]) && d.light_red[L] > 0 && d.light_red[L] <= d.light_cycle[L]))
             return fail(DP_EINVAL, "instance %d: light %d red invalid", b, L);
         if (!finite(d.light_offset[L])) return fail(DP_EINVAL, "instance %d: light %d offset invalid", b, L);
+        if (d.light_yellow) {
+            const double Y = d.light_yellow[L];
+            if (!(finite(Y) && Y >= 0 && Y <= d.light_cycle[L] - d.light_red[L]))
+                return fail(DP_EINVAL, "instance %d: light %d yellow invalid (0 <= Y <= C - R)", b, L);
+            if (Y > 0 && !(d.konst[10] < 0))
+                return fail(DP_EINVAL, "instance %d: a yellow phase needs a braking limit a_min < 0", b);
+        }
     }
     if (!(finite(d.t0_abs) && finite(d.v0) && finite(d.soc0))) return fail(DP_EINVAL, "instance %d: x0 not finite", b);
     if (!(finite(d.v_lo) && finite(d.v_hi) && d.v_lo >= 0 && d.v_hi > d.v_lo && d.n_v >= 2))
@@ -247,7 +254,7 @@ double gstep(double lo, double hi, int n) { return n > 1 ? (hi - lo) / (n - 1) :
 // Signal table of one light over the time grid [0, t_f] x n_t (Eq. 5c, 8):
 // per time node the red flag and, for a stopped vehicle, the wait to the end
 // of red in index space; FP64 on the host.
-void build_tl(double C, double R, double O, double t0_abs, double t_f, int n_t, double wt, TLEntry *out)
+void build_tl(double C, double R, double O, double Y, double t0_abs, double t_f, int n_t, double wt, TLEntry *out)
 {
     const double ht = gstep(0.0, t_f, n_t);
     for (int m = 0; m < n_t; m++) {
@@ -257,9 +264,14 @@ void build_tl(double C, double R, double O, double t0_abs, double t_f, int n_t, 
         double ph = std::fmod(t0_abs + tm - O, C);
         if (ph < 0.0) ph += C;
         e.red = ph < R ? 1 : 0;
+        // yellow: the Y seconds before red (Sec. III)
+        e.yel = !e.red && Y > 0.0 && ph >= C - Y ? 1 : 0;
+        e.ys = e.yel ? ph - (C - Y) : 0.0;
         e.wc = -1;
-        if (e.red) {
-            const double tau = R - ph;
+        // a vehicle at rest has to stop in red, and in yellow once it has
+        // begun (tl_stop at v = 0); it waits until green
+        if (e.red || (e.yel && e.ys > 0.0)) {
+            const double tau = e.red ? R - ph : (C - ph) + R;
             const double delta = tau / ht;
             const double fl = std::floor(delta);
             long c = m + (long)fl;
@@ -275,7 +287,7 @@ void build_tl(double C, double R, double O, double t0_abs, double t_f, int n_t, 
                 e.wcost = (float)(wt * tau);
                 e.wf32 = (float)f;
                 e.wg32 = (float)(1.0 - f);
-                e.ncyc = (int32_t)std::nearbyint((t0_abs + tm - O - ph) / C);
+                e.ncyc = (int32_t)std::nearbyint((t0_abs + tm - O - ph) / C) + e.yel;
             }
         }
         out[m] = e;
@@ -856,7 +868,8 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
 
     // host tables and the size of one device parameter block
     size_t param_bytes = 0, n_tl = 0;
-    std::vector<std::vector<double>> cosa(n_inst), sina(n_inst), vmax(n_inst), lc(n_inst), lr(n_inst), lo(n_inst);
+    std::vector<std::vector<double>> cosa(n_inst), sina(n_inst), vmax(n_inst), lc(n_inst), lr(n_inst), lo(n_inst),
+        ly(n_inst);
     for (int b = 0; b < n_inst; b++) {
         const dp_problem_desc &d = desc[b];
         Inst &I = p->inst[b];
@@ -879,8 +892,9 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
             lc[b].push_back(d.light_cycle[L]);
             lr[b].push_back(d.light_red[L]);
             lo[b].push_back(d.light_offset[L]);
+            ly[b].push_back(d.light_yellow ? d.light_yellow[L] : 0.0);
         }
-        param_bytes += align_up(sizeof(double) * (2 * N + (N + 1) + 3 * d.n_lights + 3), 256);
+        param_bytes += align_up(sizeof(double) * (2 * N + (N + 1) + 4 * d.n_lights + 3), 256);
         param_bytes += align_up(sizeof(int) * (N + 1), 256);
         if (d.terminal_V) param_bytes += align_up(sizeof(float) * I.S, 256);
         I.tl_dev_off = n_tl;
@@ -977,6 +991,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         dbl.insert(dbl.end(), lc[b].begin(), lc[b].end());
         dbl.insert(dbl.end(), lr[b].begin(), lr[b].end());
         dbl.insert(dbl.end(), lo[b].begin(), lo[b].end());
+        dbl.insert(dbl.end(), ly[b].begin(), ly[b].end());
         dbl.resize(dbl.size() + 3, 0.0);
         const double *dd = (const double *)put(dbl.data(), sizeof(double) * dbl.size());
         P.cosa = dd;
@@ -986,6 +1001,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         P.l_cycle = dd + 3 * N + 1;
         P.l_red = P.l_cycle + nl;
         P.l_off = P.l_red + nl;
+        P.l_yel = P.l_off + nl;
         P.light_of_stage = (const int *)put(I.light_of_stage.data(), sizeof(int) * (N + 1));
         P.terminal_V = !d.terminal_V ? nullptr
                        : (const float *)((d.flags & DP_TERMINAL_DEVICE) ? put_device(d.terminal_V, sizeof(float) * I.S)
@@ -999,8 +1015,9 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
         I.l_cycle = lc[b];
         I.l_red = lr[b];
         I.l_off = lo[b];
+        I.l_yel = ly[b];
         for (int L = 0; L < nl; L++)
-            build_tl(lc[b][L], lr[b][L], lo[b][L], d.t0_abs, d.t_f, d.n_t, d.theta[3],
+            build_tl(lc[b][L], lr[b][L], lo[b][L], ly[b][L], d.t0_abs, d.t_f, d.n_t, d.theta[3],
                      host_tl + I.tl_dev_off + (size_t)L * d.n_t);
 
         const int nst = (p->flags & DP_STORE_ALL_V) ? N + 1 : 2;
@@ -1617,7 +1634,8 @@ int dp_set_state(dp_plan *p, int32_t inst, double v0, double soc0, double t0_abs
     std::memcpy(h, &I.P, sizeof(DevInst));
     TLEntry *htl = (TLEntry *)(h + align_up(sizeof(DevInst), 256));
     for (int L = 0; L < nl; L++)
-        build_tl(I.l_cycle[L], I.l_red[L], I.l_off[L], t0_abs, I.P.t_f, I.P.n_t, I.P.wt, htl + (size_t)L * I.P.n_t);
+        build_tl(I.l_cycle[L], I.l_red[L], I.l_off[L], I.l_yel[L], t0_abs, I.P.t_f, I.P.n_t, I.P.wt,
+                 htl + (size_t)L * I.P.n_t);
     e = hipMemcpyAsync(p->dev_insts + inst, h, sizeof(DevInst), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && tl_n)
         e = hipMemcpyAsync(p->dev_tl + I.tl_dev_off, htl, sizeof(TLEntry) * tl_n, hipMemcpyHostToDevice, s);
@@ -1844,7 +1862,7 @@ int build_window_plan(const dp_problem_desc &d, int H_min, const dp_options *opt
 float *plan_terminal(dp_plan *p) { return p ? const_cast<float *>(p->inst[0].P.terminal_V) : nullptr; }
 
 int plan_set_window(dp_plan *p, const double *grade, const double *vmax, const double *cycle, const double *red,
-                    const double *offset, double t0_abs, double v0, double soc0, hipStream_t s)
+                    const double *offset, const double *yellow, double t0_abs, double v0, double soc0, hipStream_t s)
 {
     Inst &I = p->inst[0];
     const int N = I.N, nl = (int)I.l_cycle.size();
@@ -1858,14 +1876,15 @@ int plan_set_window(dp_plan *p, const double *grade, const double *vmax, const d
         if (!(std::isfinite(vmax[k]) && vmax[k] >= 0.0)) return fail(DP_EINVAL, "window: speed limit %d", k);
     for (int L = 0; L < nl; L++)
         if (!(std::isfinite(cycle[L]) && cycle[L] > 0.0 && std::isfinite(red[L]) && red[L] >= 0.0 &&
-              red[L] <= cycle[L] && std::isfinite(offset[L])))
+              red[L] <= cycle[L] && std::isfinite(offset[L]) && std::isfinite(yellow[L]) && yellow[L] >= 0.0 &&
+              yellow[L] <= cycle[L] - red[L] && (yellow[L] == 0.0 || I.P.amin < 0.0)))
             return fail(DP_EINVAL, "window: signal of stage %d", L + 1);
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     // the parameter block's per-stage arrays, in the layout of the build:
-    // cos and sin of the grade angle [N], speed limits [N+1], cycle, red and
-    // offset of every signal, three spare zeros
-    const size_t n_dbl = 3 * (size_t)N + 1 + 3 * (size_t)nl + 3;
+    // cos and sin of the grade angle [N], speed limits [N+1], cycle, red,
+    // offset and yellow of every signal, three spare zeros
+    const size_t n_dbl = 3 * (size_t)N + 1 + 4 * (size_t)nl + 3;
     const size_t tl_n = (size_t)nl * I.P.n_t;
     const size_t o_dbl = align_up(sizeof(DevInst), 256);
     const size_t o_tl = o_dbl + align_up(sizeof(double) * n_dbl, 256);
@@ -1883,18 +1902,20 @@ int plan_set_window(dp_plan *p, const double *grade, const double *vmax, const d
         dbl[3 * N + 1 + L] = cycle[L];
         dbl[3 * N + 1 + nl + L] = red[L];
         dbl[3 * N + 1 + 2 * nl + L] = offset[L];
+        dbl[3 * N + 1 + 3 * nl + L] = yellow[L];
     }
-    for (int q = 0; q < 3; q++) dbl[3 * N + 1 + 3 * nl + q] = 0.0;
+    for (int q = 0; q < 3; q++) dbl[3 * N + 1 + 4 * nl + q] = 0.0;
     I.l_cycle.assign(cycle, cycle + nl);
     I.l_red.assign(red, red + nl);
     I.l_off.assign(offset, offset + nl);
+    I.l_yel.assign(yellow, yellow + nl);
     I.P.v0 = v0;
     I.P.soc0 = soc0;
     I.P.t0_abs = t0_abs;
     std::memcpy(h, &I.P, sizeof(DevInst));
     TLEntry *htl = (TLEntry *)(h + o_tl);
     for (int L = 0; L < nl; L++)
-        build_tl(cycle[L], red[L], offset[L], t0_abs, I.P.t_f, I.P.n_t, I.P.wt, htl + (size_t)L * I.P.n_t);
+        build_tl(cycle[L], red[L], offset[L], yellow[L], t0_abs, I.P.t_f, I.P.n_t, I.P.wt, htl + (size_t)L * I.P.n_t);
     e = hipMemcpyAsync(p->dev_insts, h, sizeof(DevInst), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(const_cast<double *>(I.P.cosa), dbl, sizeof(double) * n_dbl, hipMemcpyHostToDevice, s);

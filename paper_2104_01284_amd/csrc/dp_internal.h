@@ -79,11 +79,11 @@ int api_fail(int code, const char *fmt, ...);
 // a signal at every stage 1..N-1 (placeholders until plan_set_window).
 int build_window_plan(const dp_problem_desc &d, int H_min, const dp_options *opt, int device, dp_plan **out);
 // Moves a window plan to another window of its route in place: grade [N],
-// speed limits [N+1], per stage 1..N-1 a signal (cycle, red, offset; red = 0
-// for a stage without one), clock and initial state, uploaded through the
+// speed limits [N+1], per stage 1..N-1 a signal (cycle, red, offset, yellow;
+// red = yellow = 0 for a stage without one), clock and initial state, uploaded through the
 // plan's pinned staging on stream s.  Recorded graphs pick it up on replay.
 int plan_set_window(dp_plan *p, const double *grade, const double *vmax, const double *cycle, const double *red,
-                    const double *offset, double t0_abs, double v0, double soc0, hipStream_t s);
+                    const double *offset, const double *yellow, double t0_abs, double v0, double soc0, hipStream_t s);
 // The plan's own device copy of its terminal table (DP_TERMINAL_DEVICE), or NULL.
 float *plan_terminal(dp_plan *p);
 

@@ -147,8 +147,9 @@ __global__ void k_stage_table(DevInst P, int k, StageEntry *__restrict__ st, Bat
 // node m.  For every control (wave-uniform loop, ascending u) and every SoC
 // node of the tile: Q = c + trilinear J_{k+1} at the successor, kept if
 // strictly below the running minimum (initially J_inf), so the lowest u wins a
-// tie.  Signal nodes in red are overridden at the store: J_inf for a moving
-// vehicle, the wait value (Eq. 5c) for the zero-speed row.
+// tie.  Signal nodes where the vehicle has to stop (red, or yellow past its
+// braking distance) are overridden at the store: J_inf for a moving vehicle,
+// the wait value (Eq. 5c) for the zero-speed row.
 template <int JT>
 __global__ void __launch_bounds__(1024) k_sweep_naive(DevInst P, int k, const float *__restrict__ Jn,
                                                       float *__restrict__ Jk, int16_t *__restrict__ pik,
@@ -220,13 +221,14 @@ __global__ void __launch_bounds__(1024) k_sweep_naive(DevInst P, int k, const fl
     TLEntry t;
     const bool has_tl = tl != nullptr;
     if (has_tl) t = tl[m];
+    const bool stop = has_tl && tl_stop(t, v, P.amin);
 #pragma unroll
     for (int q = 0; q < JT; q++) {
         const int j = j0 + q;
         if (j >= ns) break;
         float J = best[q];
         int pu = bu[q];
-        if (has_tl && t.red) {
+        if (stop) {
             J = Jinf;
             pu = -1;
             if (i == P.zero_row && P.wait && t.wc >= 0) {

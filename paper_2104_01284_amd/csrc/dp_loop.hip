@@ -41,13 +41,17 @@ int dev_alloc(void **ptr, size_t bytes)
     return DP_OK;
 }
 
-// Seconds until green for a vehicle at rest at a signal showing red (Eq. 8:
-// red iff (t - O) mod C in [0, R)); 0 when green.
-double red_rest(double C, double R, double O, double t)
+// Seconds until green for a vehicle at speed v that has to stop at a signal
+// at clock t, 0 when it may cross (Eq. 8: red iff (t - O) mod C in [0, R);
+// in the Y seconds of yellow before red it has to stop once more time has
+// passed since yellow began than v / (2 b), b = -a_min, Sec. III).
+double stop_time(double C, double R, double O, double Y, double amin, double v, double t)
 {
     double ph = std::fmod(t - O, C);
     if (ph < 0.0) ph += C;
-    return ph < R ? R - ph : 0.0;
+    if (ph < R) return R - ph;
+    if (Y > 0.0 && ph >= C - Y && ph - (C - Y) > v / (2.0 * -amin)) return (C - ph) + R;
+    return 0.0;
 }
 
 }  // namespace
@@ -56,7 +60,7 @@ struct dp_loop {
     int device = 0;
     hipStream_t stream = nullptr;
     dp_problem_desc route;
-    std::vector<double> grade, vmax, cyc, red, off;
+    std::vector<double> grade, vmax, cyc, red, off, yel;
     std::vector<int32_t> lstage;
     std::vector<int> light_at;          // [N_route + 1]: signal index at a route stage, or -1
     int horizon = 0;
@@ -70,7 +74,7 @@ struct dp_loop {
     size_t fslab = 0;                   // elements of one route value slab
     std::vector<Window> win;            // win[N - 1]: the plan of an N-step horizon
     double *host = nullptr;             // pinned: rollout rows 0 and 1, then V_0
-    std::vector<double> wc, wr, wo;     // a window's per-stage signals
+    std::vector<double> wc, wr, wo, wy; // a window's per-stage signals
     dp_loop_totals tot;
     bool stopped = false;
 };
@@ -134,6 +138,7 @@ int dp_loop_create(const dp_problem_desc *route, int32_t horizon, double t_f, in
         L->cyc.push_back(route->light_cycle[q]);
         L->red.push_back(route->light_red[q]);
         L->off.push_back(route->light_offset[q]);
+        L->yel.push_back(route->light_yellow ? route->light_yellow[q] : 0.0);
     }
     L->route.grade = L->grade.data();
     L->route.v_max = L->vmax.data();
@@ -141,6 +146,7 @@ int dp_loop_create(const dp_problem_desc *route, int32_t horizon, double t_f, in
     L->route.light_cycle = L->cyc.data();
     L->route.light_red = L->red.data();
     L->route.light_offset = L->off.data();
+    L->route.light_yellow = L->yel.data();
     L->route.terminal_V = nullptr;
     L->route.flags &= ~(uint32_t)DP_TERMINAL_DEVICE;
     if (route->terminal_V) {
@@ -219,6 +225,7 @@ int dp_loop_create(const dp_problem_desc *route, int32_t horizon, double t_f, in
         d.light_cycle = pc.data();
         d.light_red = pr.data();
         d.light_offset = po.data();
+        d.light_yellow = nullptr;
         d.terminal_V = dterm;
         d.flags |= DP_TERMINAL_DEVICE;
         rc = build_window_plan(d, fi.soc_shift, &wo, device, &w.p);
@@ -264,7 +271,7 @@ int dp_loop_step(dp_loop *L, dp_loop_row *row)
     double tau = 0.0;
     if (T.v == 0.0 && L->light_at[s] >= 0) {
         const int q = L->light_at[s];
-        tau = red_rest(L->cyc[q], L->red[q], L->off[q], T.t_abs);
+        tau = stop_time(L->cyc[q], L->red[q], L->off[q], L->yel[q], L->route.konst[10], 0.0, T.t_abs);
         T.t_abs += tau;
         T.wait_s += tau;
         T.cost += L->route.theta[3] * tau;
@@ -275,12 +282,14 @@ int dp_loop_step(dp_loop *L, dp_loop_row *row)
     L->wc.assign(std::max(1, N - 1), 1.0);
     L->wr.assign(std::max(1, N - 1), 0.0);
     L->wo.assign(std::max(1, N - 1), 0.0);
+    L->wy.assign(std::max(1, N - 1), 0.0);
     for (int k = 1; k < N; k++) {
         const int q = L->light_at[s + k];
         if (q >= 0) {
             L->wc[k - 1] = L->cyc[q];
             L->wr[k - 1] = L->red[q];
             L->wo[k - 1] = L->off[q];
+            L->wy[k - 1] = L->yel[q];
         }
     }
     // 3. its terminal table from the offline values J_{s+N}
@@ -289,7 +298,7 @@ int dp_loop_step(dp_loop *L, dp_loop_row *row)
                                      T.t_abs - L->route.t0_abs, L->n_t, L->t_f, L->route.konst[13], w.term, L->stream);
     if (!rc)
         rc = plan_set_window(w.p, L->grade.data() + s, L->vmax.data() + s, L->wc.data(), L->wr.data(), L->wo.data(),
-                             T.t_abs, T.v, T.soc, L->stream);
+                             L->wy.data(), T.t_abs, T.v, T.soc, L->stream);
     // 4. solve, rollout, and the first step back on the host
     if (!rc) rc = dp_solve(w.p, w.J, w.pi, w.scr, w.V0, w.u0, L->stream);
     if (!rc) rc = dp_rollout(w.p, w.pi, w.u0, w.traj, w.status, L->stream);
@@ -340,8 +349,9 @@ int dp_loop_step(dp_loop *L, dp_loop_row *row)
     if (T.stage < NR) {
         if (T.v > L->vmax[T.stage]) row->violations++;
         const int q = L->light_at[T.stage];
-        if (T.v > 0.0 && q >= 0 && red_rest(L->cyc[q], L->red[q], L->off[q], T.t_abs) > 0.0)
-            row->violations++;       // moving through a signal during red
+        if (T.v > 0.0 && q >= 0 &&
+            stop_time(L->cyc[q], L->red[q], L->off[q], L->yel[q], L->route.konst[10], T.v, T.t_abs) > 0.0)
+            row->violations++;       // moving through a signal where it has to stop
     }
     T.violations += row->violations;
     if (!(L->route.soc_lo <= T.soc && T.soc <= L->route.soc_hi)) {

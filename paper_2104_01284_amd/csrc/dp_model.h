@@ -28,7 +28,7 @@ struct DevInst {
     const double *cosa, *sina;   // [N] grade trigonometry (host FP64)
     const double *vmax;          // [N+1]
     const int *light_of_stage;   // [N+1]: signal index at stage k or -1
-    const double *l_cycle, *l_red, *l_off;
+    const double *l_cycle, *l_red, *l_off, *l_yel;
     const float *terminal_V;     // optional
 };
 
@@ -72,14 +72,27 @@ struct TLEntry {
     int32_t red;   // 1 if the node's absolute time is in a red phase
     int32_t wc;    // wait: lower time cell of t_m + tau; -1 if beyond t_f
     double wf;     // wait: fraction
-    double tau;    // wait: time to the end of red [s]
+    double tau;    // wait: time until green [s]
     float wcost;   // w_t * tau rounded to FP32
     float wf32, wg32;
-    int32_t ncyc;  // whole cycles n in t_abs - O = n C + phase (dtau/dC = n)
+    int32_t ncyc;  // dtau/dC of the wait: whole cycles n in t_abs - O = n C + phase, + 1 in yellow
+    int32_t yel;   // 1 if the node's absolute time is in a yellow phase
+    int32_t pad;
+    double ys;     // yellow: time since yellow began [s]
 };
 
+// 1 when a vehicle at speed v has to stop at the signal of entry t (Eq. 8
+// with the yellow rule of Sec. III): in red, or in yellow once more time has
+// passed since yellow began than v / (2 b), b = -a_min the braking limit (it
+// was beyond its critical braking distance v^2 / (2 b) when yellow began).
+__device__ __host__ inline bool tl_stop(const TLEntry &t, double v, double amin)
+{
+#pragma clang fp contract(off)
+    return t.red || (t.yel && t.ys > v / (2.0 * -amin));
+}
+
 // Value of waiting at a signal (the waiting cost plus the next stage's values
-// lerped at the time reached when red ends, pw pointing at the lower time
+// lerped at the time reached when green begins, pw pointing at the lower time
 // cell).  Written with explicit fused steps so that every kernel forming it
 // (sweep, control-slice combine, simple sweep) rounds the same way.
 __device__ __forceinline__ float wait_value(const TLEntry &t, const float *pw)

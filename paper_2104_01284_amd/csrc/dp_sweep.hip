@@ -666,13 +666,14 @@ __device__ __forceinline__ void sweep_item(const StageBase &B, const StageJob &j
         TLEntry t;
         const bool has_tl = tl != nullptr;
         if (has_tl) t = tl[m];
+        const bool stop = has_tl && tl_stop(t, v, PI.amin);
 #pragma unroll
         for (int q = 0; q < R; q++) {
             if (qb + q < jc) {
                 const int j = j0 + qb + q;
                 float J = best[q];
                 int pu = bu[q];
-                if (has_tl && t.red) {
+                if (stop) {
                     J = Jinf;
                     pu = -1;
                     if (i == P.zero_row && P.wait && t.wc >= 0) {
@@ -874,9 +875,14 @@ __global__ void k_sweep_combine(StageBase B)
         if (tl != nullptr) {
             const int m = (int)(n % P.n_t);
             const TLEntry t = tl[m];
-            if (t.red) {
-                const long ij = n / P.n_t;
-                const int i = (int)(ij / P.n_s);
+            const long ij = n / P.n_t;
+            const int i = (int)(ij / P.n_s);
+            double v;
+            {
+#pragma clang fp contract(off)
+                v = P.v_lo + i * P.hv;
+            }
+            if (tl_stop(t, v, P.amin)) {
                 J = Jinf;
                 pu = -1;
                 if (i == P.zero_row && P.wait && t.wc >= 0) {

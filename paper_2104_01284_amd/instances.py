@@ -281,7 +281,7 @@ def mpc_window(route: dict, s: int, t_abs: float, v: float, soc: float, horizon:
     out["N"] = N
     out["grade"] = np.array(route["grade"][s:s + N], dtype=np.float64)
     out["vmax"] = np.array(route["vmax"][s:s + N + 1], dtype=np.float64)
-    out["lights"] = [(L - s, C, R, O) for (L, C, R, O) in route["lights"] if s < L < s + N]
+    out["lights"] = [(x[0] - s,) + tuple(x[1:]) for x in route["lights"] if s < x[0] < s + N]
     out["t0_abs"] = float(t_abs)
     out["v0"] = float(v)
     out["soc0"] = float(soc)

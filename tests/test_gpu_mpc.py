@@ -133,15 +133,19 @@ def test_device_terminal_equals_host_terminal(torch):
     assert torch.equal(pa.values(0), pb.values(0)) and torch.equal(pa.policy(0), pb.policy(0))
 
 
-def test_closed_loop_matches_oracle(torch):
+@pytest.mark.parametrize("yellow", [0.0, 3.0])
+def test_closed_loop_matches_oracle(torch, yellow):
     """Twelve steps of the receding-horizon controller on a 600 m route with
-    the paper's horizon grid: the GPU loop (FP32 values, FP64 plant) and the
-    oracle's loop (FP64 throughout), each with its own full-route DP for the
-    terminal cost.  Per step V_0 within 1e-4, the same u_0* (a differing
-    choice must be a near tie at the root, after which the loops may part),
-    and the plant states within 1e-9."""
+    the paper's horizon grid (two-phase signals, and three-phase with a 3 s
+    yellow): the GPU loop (FP32 values, FP64 plant) and the oracle's loop
+    (FP64 throughout), each with its own full-route DP for the terminal cost.
+    Per step V_0 within 1e-4, the same u_0* (a differing choice must be a near
+    tie at the root, after which the loops may part), and the plant states
+    within 1e-9."""
     from paper_2104_01284_amd.mpc import ClosedLoop
     route = ins.mpc_route(seed=9, length_m=600.0, n_lights=2)
+    if yellow:
+        route = ins.with_yellow(route, yellow)
     steps = 12
     say("closed loop on", route["name"], "N", route["N"], "lights", route["lights"])
     loop = ClosedLoop(route).run(steps)

@@ -549,3 +549,41 @@ def test_adjoint_central_differences_on_gpu(torch):
                 checked += 1
                 break
     assert checked >= 4
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_yellow_phase_end_to_end_and_isolated(torch, kernel):
+    """Three-phase signal (an 8 s yellow before red, Sec. III's yellow rule)
+    on the 500 m instance: end-to-end V_0 and J, every stage isolated, and the
+    signal-timing sensitivities against the oracle, for both sweep kernels;
+    the signal stage holds yellow nodes that block slow rows and pass fast
+    ones."""
+    inst = ins.plain_yellow()
+    k_l = inst["lights"][0][0]
+    say("plain_yellow kernel", kernel)
+    r = oracle.solve(inst, q2=True)
+    plan = Plan([inst], store_all=True, kernel=kernel)
+    V0, u0 = plan.solve()
+    torch.cuda.synchronize()
+    assert abs(float(V0.cpu()[0]) - r["V0"]) <= 1e-4 * abs(r["V0"])
+    J = plan.values(0).cpu().numpy().astype(np.float64)
+    err = np.abs(J - r["J"]) / np.maximum(1.0, np.abs(r["J"]))
+    assert err.max() < 1e-4, float(err.max())
+    # the signal stage: yellow blocks some moving rows and passes others
+    two = oracle.solve(ins.plain(), q2=False)
+    Jinf = inst["konst"][13]
+    diff = (r["J"][k_l] != two["J"][k_l])
+    assert diff.any() and (r["J"][k_l][diff] == Jinf).any()
+    for k in range(inst["N"]):
+        check_stage_isolated(torch, plan, inst, 0, k, r["J"][k + 1].astype(np.float32), "plain_yellow")
+    # rollout and signal-timing sensitivities on the oracle's own solve
+    load_oracle_solution(torch, plan, inst, r)
+    trajs, status = plan.rollout()
+    _, dsp = plan.adjoint_spat()
+    torch.cuda.synchronize()
+    ro = oracle.rollout(inst, r["pi"], r["u0"])
+    assert int(status.cpu()[0, 0]) == ro["status"] and int(status.cpu()[0, 1]) == ro["violations"]
+    np.testing.assert_allclose(trajs[0].cpu().numpy()[:, :3], ro["traj"][:, :3], rtol=1e-9, atol=1e-9)
+    J32 = r["J"].astype(np.float32).astype(np.float64)
+    ds_o = oracle.adjoint(inst, J32, r["pi"], r["u0"])["dspat"]
+    np.testing.assert_allclose(dsp[0].cpu().numpy(), ds_o, rtol=1e-9, atol=1e-12)
