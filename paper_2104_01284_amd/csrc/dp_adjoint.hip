@@ -498,12 +498,12 @@ __global__ void __launch_bounds__(256) k_adj_table(DevInst P, int k, AdjEntry *_
 // later), and then runs the FP64 work on full waves: per node the (i, u)
 // entry of the stage table, the battery current and SoC cell (Eq. 5b), the
 // interpolation gradient and the scatter.
-constexpr int kAdjChunk = 1024;
+constexpr int kAdjChunk = 1024, kAdjThreads = 256;
 
 // SPAT: also the signal-timing sums of the wait nodes (a separate instance, so
 // that the plain adjoint keeps its registers).
 template <bool SPAT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__restrict__ pik,
             const TLEntry *__restrict__ tl, const AdjEntry *__restrict__ tab, double *__restrict__ rho,
             double *__restrict__ rho_next, double *__restrict__ gacc, double *__restrict__ gcrr,
@@ -512,6 +512,9 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
 #pragma clang fp contract(off)
     __shared__ int s_list[kAdjChunk];
     __shared__ double s_rho[kAdjChunk];
+    __shared__ short s_slot[kAdjChunk];          // chunk position -> list slot, -1 if unoccupied
+    __shared__ int s_key[3][kAdjThreads];        // per slot of the pass: successor speed, SoC, time cell
+    __shared__ double s_up[4][kAdjThreads];      // per slot of the pass: its upper-SoC terms
     __shared__ int s_cnt;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double sO = 0.0, sC = 0.0;   // signal timing: sum of rho dval/dtau, and of rho n dval/dtau
@@ -520,40 +523,42 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
     for (long c0 = blockIdx.x * (long)kAdjChunk; c0 < S; c0 += (long)gridDim.x * kAdjChunk) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
-        for (int j = threadIdx.x; j < kAdjChunk; j += blockDim.x) {
-            const long n = c0 + j;
+        for (int jj = threadIdx.x; jj < kAdjChunk; jj += blockDim.x) {
+            const long n = c0 + jj;
             const double r = n < S ? rho[n] : 0.0;
             const bool act = r > 0.0;
             const unsigned long long msk = __ballot(act);
             int off = 0;
             if (lane == 0 && msk) off = atomicAdd(&s_cnt, __popcll(msk));
             off = __shfl(off, 0);
+            s_slot[jj] = -1;
             if (act) {
                 const int slot = off + __popcll(msk & ((1ull << lane) - 1ull));
-                s_list[slot] = j;
+                s_list[slot] = jj;
                 s_rho[slot] = r;
+                s_slot[jj] = (short)slot;
                 rho[n] = 0.0;
             }
         }
         __syncthreads();
         const int na = s_cnt;
         // Waves walk the list together (every lane takes part in the
-        // exchanges below, past the list's end too).  Occupied nodes come in
-        // node order within a wave's share, so neighbouring lanes often hold
-        // nodes m - 1 and m of one (speed, SoC) row under the same control:
-        // their successors then share speed and SoC cells and weights and sit
-        // one time cell apart, and the upper time corners of the first are the
-        // lower corners of the second.  The second lane adds the first's four
-        // upper terms into its own four lower atomics and the first skips
-        // them: one add per shared cell instead of two.
+        // exchanges below, past the list's end too), a pass of kAdjThreads
+        // list slots at a time.  Occupied nodes come in node order, so
+        // neighbouring lanes often hold nodes m - 1 and m of one (speed, SoC)
+        // row under the same control, and the slot of the node one SoC row
+        // down is usually in the same pass: their successors then share
+        // corner cells.  Terms that go to one cell are added up first and
+        // sent with one atomic (time neighbours through shuffles, SoC
+        // neighbours through LDS).
         for (int a0 = 0; a0 < na; a0 += blockDim.x) {
             const int a = a0 + (int)threadIdx.x;
             const bool live = a < na;
-            const int jj = live ? s_list[a] : -2;
+            const int jj = live ? s_list[a] : 0;
             const long n = c0 + jj;
             const double r = live ? s_rho[a] : 0.0;
-            const int m = live ? (int)(n % P.n_t) : 0;
-            const long ij = live ? n / P.n_t : 0;
+            const int m = (int)(n % P.n_t);
+            const long ij = n / P.n_t;
             const int j = (int)(ij % P.n_s);
             const int i = (int)(ij / P.n_s);
             const int u = live ? (int)pik[n] : -1;
@@ -609,39 +614,64 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
                     }
                 }
             }
-            // this lane's upper time corners (speed corner a, SoC corner b)
-            double up[4];
-            for (int q = 0; q < 4; q++) {
-                const int ca = q >> 1, cb = q & 1;
+            // the eight terms t[(ca * 2 + cb) * 2 + ce] for speed, SoC and time
+            // corners ca, cb, ce of the successor cell (0 where a weight is 0)
+            double t[8];
+            for (int q = 0; q < 8; q++) {
+                const int ca = q >> 2, cb = (q >> 1) & 1, ce = q & 1;
                 const double wa = ca ? x.f[0] : 1.0 - x.f[0];
                 const double wb = cb ? x.f[1] : 1.0 - x.f[1];
-                up[q] = scat && wa > 0.0 && wb > 0.0 && x.f[2] > 0.0 ? r * wa * wb * x.f[2] : 0.0;
+                const double we = ce ? x.f[2] : 1.0 - x.f[2];
+                t[q] = scat && wa > 0.0 && wb > 0.0 && we > 0.0 ? r * wa * wb * we : 0.0;
             }
-            // does the previous lane hold node n - 1 of this row under the same
-            // control, with its successor one time cell below this one's at the
-            // same time fraction (then all other weights agree as well)?
-            const int p_jj = __shfl_up(jj, 1);
-            const int p_u = __shfl_up(u, 1);
-            const int p_tc = __shfl_up(x.c[2], 1);
-            const double p_ft = __shfl_up(x.f[2], 1);
-            const int p_scat = __shfl_up((int)scat, 1);
-            double p_up[4];
-            for (int q = 0; q < 4; q++) p_up[q] = __shfl_up(up[q], 1);
-            const bool merge = scat && lane > 0 && p_scat && m > 0 && p_jj == jj - 1 && p_u == u &&
-                               p_tc == x.c[2] - 1 && p_ft == x.f[2];
-            const bool absorbed = __shfl_down((int)merge, 1) && lane < 63;
-            if (scat) {
+            const int kcv = scat ? x.c[0] : -1;
+            // time merge: the previous lane's successor lies one time cell
+            // below this one in the same speed and SoC cells (its upper time
+            // corners are this lane's lower ones)
+            {
+                const int p_cv = __shfl_up(kcv, 1);
+                const int p_cs = __shfl_up(x.c[1], 1);
+                const int p_tc = __shfl_up(x.c[2], 1);
+                double p_up[4];
+                for (int q = 0; q < 4; q++) p_up[q] = __shfl_up(t[q * 2 + 1], 1);
+                const bool merge = scat && lane > 0 && p_cv == kcv && p_cs == x.c[1] && p_tc == x.c[2] - 1;
+                const bool absorbed = __shfl_down((int)merge, 1) && lane < 63;
                 for (int q = 0; q < 4; q++) {
-                    const int ca = q >> 1, cb = q & 1;
-                    const double wa = ca ? x.f[0] : 1.0 - x.f[0];
-                    const double wb = cb ? x.f[1] : 1.0 - x.f[1];
-                    double *dst = rho_next + ((long)(x.c[0] + ca) * P.n_s + (x.c[1] + cb)) * P.n_t + x.c[2];
-                    double lo = wa > 0.0 && wb > 0.0 && 1.0 - x.f[2] > 0.0 ? r * wa * wb * (1.0 - x.f[2]) : 0.0;
-                    if (merge) lo += p_up[q];
-                    if (lo > 0.0) unsafeAtomicAdd(dst, lo);
-                    if (!absorbed && up[q] > 0.0) unsafeAtomicAdd(dst + 1, up[q]);
+                    if (merge) t[q * 2] += p_up[q];
+                    if (absorbed) t[q * 2 + 1] = 0.0;
                 }
             }
+            // SoC merge through LDS, between slots of this pass: the node one
+            // SoC row down, if its successor lies one SoC cell below this one
+            // in the same speed and time cells, sends its upper-SoC terms
+            const int sl = a - a0;
+            if (live) {
+                s_key[0][sl] = kcv;
+                s_key[1][sl] = x.c[1];
+                s_key[2][sl] = x.c[2];
+                for (int ca = 0; ca < 2; ca++)
+                    for (int ce = 0; ce < 2; ce++) s_up[ca * 2 + ce][sl] = t[(ca * 2 + 1) * 2 + ce];
+            }
+            __syncthreads();
+            if (scat) {
+                const int pp = jj - P.n_t, pn = jj + P.n_t;
+                const int sp = pp >= 0 ? (int)s_slot[pp] - a0 : -1;
+                const int ss = pn < kAdjChunk ? (int)s_slot[pn] - a0 : -1;
+                const bool take = sp >= 0 && sp < kAdjThreads && s_key[0][sp] == kcv && s_key[1][sp] == x.c[1] - 1 &&
+                                  s_key[2][sp] == x.c[2];
+                const bool give = ss >= 0 && ss < kAdjThreads && s_key[0][ss] == kcv && s_key[1][ss] == x.c[1] + 1 &&
+                                  s_key[2][ss] == x.c[2];
+                for (int q = 0; q < 8; q++) {
+                    const int ca = q >> 2, cb = (q >> 1) & 1, ce = q & 1;
+                    double v = t[q];
+                    if (cb == 0 && take) v += s_up[ca * 2 + ce][sp];
+                    if (cb == 1 && give) v = 0.0;
+                    if (v > 0.0)
+                        unsafeAtomicAdd(
+                            rho_next + ((long)(x.c[0] + ca) * P.n_s + (x.c[1] + cb)) * P.n_t + (x.c[2] + ce), v);
+                }
+            }
+            __syncthreads();   // the pass's keys are read before the next pass rewrites them
         }
         __syncthreads();   // the list is read before the next chunk rewrites it
     }
@@ -726,11 +756,11 @@ int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t
     double *gcrr = gstage ? gstage + (long)k * kAdjBlocks : nullptr;
     const AdjEntry *t = (const AdjEntry *)tab;
     if (tl && gspat_L)
-        hipLaunchKernelGGL(k_adj_stage<true>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, t, rho, rho_next,
-                           gacc, gcrr, gspat_L);
+        hipLaunchKernelGGL(k_adj_stage<true>, dim3(kAdjBlocks), dim3(kAdjThreads), 0, s, P, k, Jn, pik, tl, t, rho,
+                           rho_next, gacc, gcrr, gspat_L);
     else
-        hipLaunchKernelGGL(k_adj_stage<false>, dim3(kAdjBlocks), dim3(256), 0, s, P, k, Jn, pik, tl, t, rho, rho_next,
-                           gacc, gcrr, nullptr);
+        hipLaunchKernelGGL(k_adj_stage<false>, dim3(kAdjBlocks), dim3(kAdjThreads), 0, s, P, k, Jn, pik, tl, t, rho,
+                           rho_next, gacc, gcrr, nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
