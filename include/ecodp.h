@@ -77,6 +77,9 @@ enum {
                                   every queue waits for a count that is never reached, gives up after
                                   1000 polls and sets the device error word (dp_device_check reports
                                   DP_EDEVICE); the solve's results are then not valid */
+#define DP_ADJOINT_WIDE 32u    /* the adjoint's stage kernel takes 2048-node chunks whatever the grid
+                                  (chosen by itself on grids of at least 4 Mi nodes per stage); the
+                                  gradient is the same up to the order of FP64 additions */
 
 /* One receding-horizon problem (Eq. 6-8).  Host pointers; copied at build. */
 typedef struct {

@@ -20,6 +20,7 @@ DP_TIMING = 2
 DP_GRAPH = 4
 DP_ROUNDS = 8
 DP_STALL_TEST = 16
+DP_ADJOINT_WIDE = 32
 
 EXPORTS = ("dp_build_problem", "dp_workspace_size", "dp_instance_info_get", "dp_solve", "dp_solve_static",
            "dp_stage", "dp_set_state", "dp_terminal_from_values", "dp_rollout", "dp_adjoint", "dp_adjoint_grade",

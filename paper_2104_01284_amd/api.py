@@ -111,7 +111,8 @@ class Plan:
 
     def __init__(self, instances, store_all: bool = False, timing: bool = False, device: int = 0,
                  sweep_tile: int = 0, kernel: int = 0, split: int = 0, wg_per_cu: int = 0,
-                 graph: bool = False, inst_opts=None, rounds: bool = False, stall_test: bool = False):
+                 graph: bool = False, inst_opts=None, rounds: bool = False, stall_test: bool = False,
+                 adjoint_wide: bool = False):
         import torch
         self.torch = torch
         if isinstance(instances, dict):
@@ -122,7 +123,8 @@ class Plan:
         arr = (L.DpProblemDesc * len(self._descs))(*[x.d for x in self._descs])
         opt = L.DpOptions()
         opt.flags = (L.DP_STORE_ALL_V if store_all else 0) | (L.DP_TIMING if timing else 0) | \
-            (L.DP_GRAPH if graph else 0) | (L.DP_ROUNDS if rounds else 0) | (L.DP_STALL_TEST if stall_test else 0)
+            (L.DP_GRAPH if graph else 0) | (L.DP_ROUNDS if rounds else 0) | (L.DP_STALL_TEST if stall_test else 0) | \
+            (L.DP_ADJOINT_WIDE if adjoint_wide else 0)
         opt.tile[0] = int(sweep_tile)
         opt.tile[1] = int(split)
         opt.tile[2] = int(wg_per_cu)

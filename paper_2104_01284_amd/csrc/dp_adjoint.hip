@@ -492,27 +492,30 @@ __global__ void __launch_bounds__(256) k_adj_table(DevInst P, int k, AdjEntry *_
 // gradient terms weighted by rho, and rho times the interpolation weights
 // added to the stage k+1 occupancy.  Wait nodes add rho * tau to dV/dw_t and
 // move in time only.  Nodes without a control keep J_inf and stop the mass.
-// Each workgroup takes a chunk of kAdjChunk consecutive nodes, gathers the
+// Each workgroup takes a chunk of CHUNK consecutive nodes, gathers the
 // ones with rho > 0 (and their rho) into LDS lists, zeroing them in rho (so
 // that the buffer is all zero again when it becomes the occupancy two stages
 // later), and then runs the FP64 work on full waves: per node the (i, u)
 // entry of the stage table, the battery current and SoC cell (Eq. 5b), the
 // interpolation gradient and the scatter.
-constexpr int kAdjChunk = 1024, kAdjThreads = 256;
+constexpr int kAdjThreads = 256;
 
 // SPAT: also the signal-timing sums of the wait nodes (a separate instance, so
-// that the plain adjoint keeps its registers).
-template <bool SPAT>
-__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(5, 8)))
+// that the plain adjoint keeps its registers).  CHUNK: 1024 nodes, or 2048 on
+// grids with at least two such chunks per workgroup (more SoC-row neighbours
+// in one chunk, at four workgroups per CU instead of five).
+template <bool SPAT, int CHUNK>
+__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(CHUNK > 1024 ? 4 : 5, 8)))
 k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__restrict__ pik,
             const TLEntry *__restrict__ tl, const AdjEntry *__restrict__ tab, double *__restrict__ rho,
             double *__restrict__ rho_next, double *__restrict__ gacc, double *__restrict__ gcrr,
             double *__restrict__ gspat)
 {
 #pragma clang fp contract(off)
-    __shared__ int s_list[kAdjChunk];
-    __shared__ double s_rho[kAdjChunk];
-    __shared__ short s_slot[kAdjChunk];          // chunk position -> list slot, -1 if unoccupied
+    __shared__ short s_list[CHUNK];              // list slot -> chunk position
+    __shared__ double s_rho[CHUNK];
+    __shared__ short s_slot[CHUNK];              // chunk position -> list slot, -1 if unoccupied
+    __shared__ short s_u[CHUNK];                 // list slot -> stored control
     __shared__ int s_key[3][kAdjThreads];        // per slot of the pass: successor speed, SoC, time cell
     __shared__ double s_up[4][kAdjThreads];      // per slot of the pass: its upper-SoC terms
     __shared__ int s_cnt;
@@ -520,13 +523,22 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
     double sO = 0.0, sC = 0.0;   // signal timing: sum of rho dval/dtau, and of rho n dval/dtau
     const long S = (long)P.n_v * P.n_s * P.n_t;
     const int lane = threadIdx.x & 63;
-    for (long c0 = blockIdx.x * (long)kAdjChunk; c0 < S; c0 += (long)gridDim.x * kAdjChunk) {
+    for (long c0 = blockIdx.x * (long)CHUNK; c0 < S; c0 += (long)gridDim.x * CHUNK) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
-        for (int jj = threadIdx.x; jj < kAdjChunk; jj += blockDim.x) {
-            const long n = c0 + jj;
-            const double r = n < S ? rho[n] : 0.0;
-            const bool act = r > 0.0;
+        // all loads of the chunk's occupancy in flight at once, then the
+        // controls of the occupied nodes
+        constexpr int kPer = CHUNK / kAdjThreads;
+        double rv[kPer];
+        for (int q = 0; q < kPer; q++) {
+            const long n = c0 + q * kAdjThreads + threadIdx.x;
+            rv[q] = n < S ? rho[n] : 0.0;
+        }
+        int16_t uv[kPer];
+        for (int q = 0; q < kPer; q++) uv[q] = rv[q] > 0.0 ? pik[c0 + q * kAdjThreads + threadIdx.x] : (int16_t)-1;
+        for (int q = 0; q < kPer; q++) {
+            const int jj = q * kAdjThreads + (int)threadIdx.x;
+            const bool act = rv[q] > 0.0;
             const unsigned long long msk = __ballot(act);
             int off = 0;
             if (lane == 0 && msk) off = atomicAdd(&s_cnt, __popcll(msk));
@@ -534,10 +546,11 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
             s_slot[jj] = -1;
             if (act) {
                 const int slot = off + __popcll(msk & ((1ull << lane) - 1ull));
-                s_list[slot] = jj;
-                s_rho[slot] = r;
+                s_list[slot] = (short)jj;
+                s_rho[slot] = rv[q];
+                s_u[slot] = uv[q];
                 s_slot[jj] = (short)slot;
-                rho[n] = 0.0;
+                rho[c0 + jj] = 0.0;
             }
         }
         __syncthreads();
@@ -561,7 +574,7 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
             const long ij = n / P.n_t;
             const int j = (int)(ij % P.n_s);
             const int i = (int)(ij / P.n_s);
-            const int u = live ? (int)pik[n] : -1;
+            const int u = live ? (int)s_u[a] : -1;
             bool scat = false;     // a regular successor whose 8 corners this lane scatters
             Cells x;
             x.c[0] = x.c[1] = x.c[2] = 0;
@@ -656,7 +669,7 @@ k_adj_stage(DevInst P, int k, const float *__restrict__ Jn, const int16_t *__res
             if (scat) {
                 const int pp = jj - P.n_t, pn = jj + P.n_t;
                 const int sp = pp >= 0 ? (int)s_slot[pp] - a0 : -1;
-                const int ss = pn < kAdjChunk ? (int)s_slot[pn] - a0 : -1;
+                const int ss = pn < CHUNK ? (int)s_slot[pn] - a0 : -1;
                 const bool take = sp >= 0 && sp < kAdjThreads && s_key[0][sp] == kcv && s_key[1][sp] == x.c[1] - 1 &&
                                   s_key[2][sp] == x.c[2];
                 const bool give = ss >= 0 && ss < kAdjThreads && s_key[0][ss] == kcv && s_key[1][ss] == x.c[1] + 1 &&
@@ -749,18 +762,30 @@ int launch_adjoint_table(const DevInst &P, int k, void *tab, hipStream_t s)
 
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
                          const void *tab, double *rho, double *rho_next, double *gacc, double *gstage,
-                         double *gspat_L, hipStream_t s)
+                         double *gspat_L, bool force_wide, hipStream_t s)
 {
     // kAdjBlocks workgroups walk the chunks, each adding into its own slot
     // (and, at a signal, storing its pair of gspat_L)
     double *gcrr = gstage ? gstage + (long)k * kAdjBlocks : nullptr;
     const AdjEntry *t = (const AdjEntry *)tab;
-    if (tl && gspat_L)
-        hipLaunchKernelGGL(k_adj_stage<true>, dim3(kAdjBlocks), dim3(kAdjThreads), 0, s, P, k, Jn, pik, tl, t, rho,
-                           rho_next, gacc, gcrr, gspat_L);
-    else
-        hipLaunchKernelGGL(k_adj_stage<false>, dim3(kAdjBlocks), dim3(kAdjThreads), 0, s, P, k, Jn, pik, tl, t, rho,
-                           rho_next, gacc, gcrr, nullptr);
+    const long S = (long)P.n_v * P.n_s * P.n_t;
+    const bool wide = force_wide || S >= 2L * 2048 * kAdjBlocks;
+    const dim3 g(kAdjBlocks), b(kAdjThreads);
+    if (tl && gspat_L) {
+        if (wide)
+            hipLaunchKernelGGL((k_adj_stage<true, 2048>), g, b, 0, s, P, k, Jn, pik, tl, t, rho, rho_next, gacc, gcrr,
+                               gspat_L);
+        else
+            hipLaunchKernelGGL((k_adj_stage<true, 1024>), g, b, 0, s, P, k, Jn, pik, tl, t, rho, rho_next, gacc, gcrr,
+                               gspat_L);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((k_adj_stage<false, 2048>), g, b, 0, s, P, k, Jn, pik, tl, t, rho, rho_next, gacc, gcrr,
+                               nullptr);
+        else
+            hipLaunchKernelGGL((k_adj_stage<false, 1024>), g, b, 0, s, P, k, Jn, pik, tl, t, rho, rho_next, gacc, gcrr,
+                               nullptr);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

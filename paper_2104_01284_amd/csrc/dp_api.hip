@@ -822,7 +822,7 @@ int dp_build_problem(const dp_problem_desc *desc, int32_t n_inst, const dp_optio
     if (!out) return fail(DP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!desc || n_inst < 1) return fail(DP_EINVAL, "need at least one problem description");
-    if (opt && (opt->flags & ~(DP_STORE_ALL_V | DP_TIMING | DP_GRAPH | DP_ROUNDS | DP_STALL_TEST)))
+    if (opt && (opt->flags & ~(DP_STORE_ALL_V | DP_TIMING | DP_GRAPH | DP_ROUNDS | DP_STALL_TEST | DP_ADJOINT_WIDE)))
         return fail(DP_EINVAL, "unknown option flags");
     if (opt && (opt->flags & DP_GRAPH) && (opt->flags & DP_TIMING))
         return fail(DP_EINVAL, "option flags DP_GRAPH and DP_TIMING exclude each other");
@@ -1716,8 +1716,7 @@ static int adjoint_impl(dp_plan *p, const void *J, const void *pi, const int16_t
                 return hip_fail(hipGetLastError(), "adjoint table launch");
             double *gspat_L = gspat && L >= 0 ? gspat + 2 * adjoint_grade_slots() * (size_t)L : nullptr;
             if (launch_adjoint_stage(I.P, k, Jb + (size_t)(k + 1) * I.S, pib + (size_t)k * I.S, tl, tab, rho_a, rho_b,
-                                     gpart,
-                                     gstage, gspat_L, s))
+                                     gpart, gstage, gspat_L, (p->flags & DP_ADJOINT_WIDE) != 0, s))
                 return hip_fail(hipGetLastError(), "adjoint stage launch");
             double *t = rho_a;
             rho_a = rho_b;

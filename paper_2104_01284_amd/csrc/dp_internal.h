@@ -59,7 +59,7 @@ size_t adjoint_table_bytes(const DevInst &P);
 int launch_adjoint_table(const DevInst &P, int k, void *tab, hipStream_t s);
 int launch_adjoint_stage(const DevInst &P, int k, const float *Jn, const int16_t *pik, const TLEntry *tl,
                          const void *tab, double *rho, double *rho_next, double *gacc, double *gstage,
-                         double *gspat_L, hipStream_t s);
+                         double *gspat_L, bool wide, hipStream_t s);
 // dspat[3 L + (0, 1, 2)] = dV/d(offset, red, cycle) of signal L from the
 // adjoint_grade_slots() slot pairs per signal in gspat.
 int launch_adjoint_spat(int n_lights, const double *gspat, const double *grad, double *dspat, hipStream_t s);

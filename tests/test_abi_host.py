@@ -143,7 +143,7 @@ def test_no_device_is_edevice(lib):
 
 
 @pytest.mark.parametrize("kw,needle", [
-    (dict(flags=32), "flags"),
+    (dict(flags=64), "flags"),
     (dict(kernel=4), "kernel"),
     (dict(flags=6), "exclude"),
     (dict(kernel=-1), "kernel"),

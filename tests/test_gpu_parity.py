@@ -203,11 +203,12 @@ def test_rollout_matches_oracle_given_oracle_policy(torch):
         np.testing.assert_allclose(tg[both], to[both], rtol=1e-9, atol=1e-9)
 
 
-def test_adjoint_matches_oracle_given_oracle_values(torch):
+@pytest.mark.parametrize("wide", [False, True], ids=["chunk1024", "chunk2048"])
+def test_adjoint_matches_oracle_given_oracle_values(torch, wide):
     for inst in [ins.plain()] + ragged_instances()[:1]:
-        say("adjoint", inst["name"])
+        say("adjoint", inst["name"], "2048-node chunks" if wide else "")
         r = oracle.solve(inst)
-        plan = Plan([inst], store_all=True)
+        plan = Plan([inst], store_all=True, adjoint_wide=wide)
         plan.solve()
         load_oracle_solution(torch, plan, inst, r)
         g = plan.adjoint()
@@ -429,7 +430,8 @@ def test_grade_sensitivities_match_oracle(torch):
         np.testing.assert_allclose(g5.cpu().numpy()[0], ao["grad"], rtol=1e-9, atol=1e-12)
 
 
-def test_signal_timing_sensitivities_match_oracle(torch):
+@pytest.mark.parametrize("wide", [False, True], ids=["chunk1024", "chunk2048"])
+def test_signal_timing_sensitivities_match_oracle(torch, wide):
     """dV_0 with respect to each signal's offset, red time and cycle
     (dp_adjoint_spat) on the oracle's own solve loaded into the plan, against
     the oracle's adjoint on the same FP32-rounded values (1e-9): a route whose
@@ -446,9 +448,9 @@ def test_signal_timing_sensitivities_match_oracle(torch):
     t0 = w["t0_abs"]
     w["lights"] = [(1, 35.0, 20.0, t0 - 3.0), (7, 30.0, 14.0, t0 - 35.0), (12, 25.0, 15.0, t0 - 40.0)]
     for group in ([t], [flat, t], [w]):
-        say("signal-timing sensitivities", [x["name"] for x in group])
+        say("signal-timing sensitivities", [x["name"] for x in group], "2048-node chunks" if wide else "")
         sols = [oracle.solve(x) for x in group]
-        plan = Plan(group, store_all=True)
+        plan = Plan(group, store_all=True, adjoint_wide=wide)
         plan.solve()
         for b, (x, r) in enumerate(zip(group, sols)):
             plan.values(b).copy_(torch.from_numpy(r["J"].astype(np.float32)).cuda())
