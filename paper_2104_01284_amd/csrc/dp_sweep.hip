@@ -494,22 +494,21 @@ __device__ __forceinline__ void sweep_item(const StageBase &B, const StageJob &j
         // each control: one LDS load of the wave's 2R weights (lane l takes
         // weight l mod 2R) and one of the record's scalars and cells (lane l
         // takes word l mod 16 after the weights), issued one control ahead
-        float Wn = 0.0f, Sn = 0.0f;
+        float W = 0.0f, S = 0.0f;
         if (cn > 0) {
-            Wn = chunk[wofs + wlane];
-            Sn = chunk[rec_scalars(JT) + slane];
+            W = chunk[wofs + wlane];
+            S = chunk[rec_scalars(JT) + slane];
         }
         for (int cr = 0; cr < cn; cr++) {
-            const float W = Wn, S = Sn;
             const int ivdtc = __builtin_amdgcn_readlane(__float_as_int(S), kScIvDtc);
             const int uhdr = __builtin_amdgcn_readlane(__float_as_int(S), kScUHdr);
-            if (cr + 1 < cn) {
-                const float *nx = chunk + (cr + 1) * CW;
-                Wn = nx[wofs + wlane];
-                Sn = nx[rec_scalars(JT) + slane];
-            }
+            const float *nx = chunk + min(cr + 1, cn - 1) * CW;
             const int hdr = uhdr >> 16;
-            if (hdr == kRecEmpty) continue;          // no row of this tile has a successor
+            if (hdr == kRecEmpty) {                  // no row of this tile has a successor
+                W = nx[wofs + wlane];
+                S = nx[rec_scalars(JT) + slane];
+                continue;
+            }
             nrec++;
             const int p = ivdtc & 0xffff;
             const int dtc = ivdtc >> 16;
@@ -641,6 +640,9 @@ __device__ __forceinline__ void sweep_item(const StageBase &B, const StageJob &j
                     }
                 }
             }
+            // the next control's record, in flight during the minimum update
+            W = nx[wofs + wlane];
+            S = nx[rec_scalars(JT) + slane];
 #pragma unroll
             for (int q = 0; q < R; q++) {
                 const bool upd = Qv[q] < best[q];
