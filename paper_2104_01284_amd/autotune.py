@@ -136,26 +136,33 @@ def batch_key(instances, device_name: str) -> str:
     return f"{device_name}|batch{len(instances)}|{hashlib.sha256(shapes.encode()).hexdigest()[:16]}"
 
 
-def tune_batch(instances, device: int = 0, tiles=BATCH_TILES, repeats: int = 1) -> dict:
-    """Whole solves of the batch with every instance on one SoC tile (after
-    one untimed solve each); returns the fastest as {"tile", "ms", "all"}."""
+def tune_batch(instances, device: int = 0, tiles=BATCH_TILES, repeats: int = 2) -> dict:
+    """Whole solves of the batch with every instance on one SoC tile, replayed
+    as recorded graphs the way a batch is solved; after two untimed solves of
+    every candidate, the candidates are timed in turn `repeats` times and each
+    keeps its fastest solve (so that clock ramp-up or a one-off stall does not
+    land on whichever candidate happens to run first).  Returns the fastest
+    as {"tile", "ms", "all"}."""
     import torch
     from .api import Plan
-    results = {}
-    for t in tiles:
-        plan = Plan(instances, sweep_tile=t, device=device)
-        plan.solve()
-        torch.cuda.synchronize(device)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(repeats):
+    plans = {t: Plan(instances, sweep_tile=t, graph=True, device=device) for t in tiles}
+    for plan in plans.values():
+        for _ in range(2):
             plan.solve()
-        b.record()
-        torch.cuda.synchronize(device)
-        results[str(t)] = a.elapsed_time(b) / repeats
-        del plan
-        torch.cuda.empty_cache()
+    torch.cuda.synchronize(device)
+    results = {}
+    for _ in range(repeats):
+        for t, plan in plans.items():
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            plan.solve()
+            b.record()
+            torch.cuda.synchronize(device)
+            ms = a.elapsed_time(b)
+            results[str(t)] = min(ms, results.get(str(t), ms))
+    del plans
+    torch.cuda.empty_cache()
     best = min(results, key=results.get)
     return {"tile": int(best), "ms": results[best], "all": results}
 
