@@ -350,7 +350,9 @@ __device__ inline void block_add5(double g[5], double *gpart, double *gcrr = nul
     if (threadIdx.x < 5) {
         double x = 0.0;
         for (int ww = 0; ww < nw; ww++) x += red[ww][threadIdx.x];
-        gpart[(long)blockIdx.x * 5 + threadIdx.x] += x;
+        // the workgroup's own slot, one launch at a time: an add without a
+        // returned value, so the workgroup does not wait on a read of it
+        unsafeAtomicAdd(&gpart[(long)blockIdx.x * 5 + threadIdx.x], x);
         if (gcrr && threadIdx.x == 2) gcrr[blockIdx.x] = x;
     }
 }

@@ -255,6 +255,17 @@ def test_autograd_function(torch):
     # against the FP64 tangent of the oracle's own solve (policy may differ at near-ties)
     gt = oracle.tangent(inst, r["J"], r["pi"], r["u0"])
     np.testing.assert_allclose(theta.grad.numpy(), gt, rtol=2e-3)
+    # the chain rule through the function: loss = 0.5 (V - c)^2 * w with theta
+    # entering twice (scaled copies), so the upstream gradient is not one and
+    # the two paths' gradients add
+    c, w = 100.0, 2.5
+    th = torch.tensor(inst["theta"], dtype=torch.float64, requires_grad=True)
+    scale = torch.tensor([1.0, 1.0, 1.0, 1.0, 1.0], dtype=torch.float64)
+    V2 = EcoDPValue.apply(th * scale, inst)
+    loss = 0.5 * w * (V2 - c) ** 2 + 3.0 * EcoDPValue.apply(th, inst)
+    loss.backward()
+    want = (w * (V2.item() - c) + 3.0) * g
+    np.testing.assert_allclose(th.grad.numpy(), want, rtol=1e-11)
 
 
 def test_multi_instance_plan_equals_single(torch):
