@@ -107,7 +107,11 @@ typedef struct {
                                   the crank speed omega of the step's initial speed (0 = no cap) */
     double fuel[6];            /* fuel rate q0 + q1 v + q2 T + q3 v^2 + q4 v T + q5 T^2 [g/s], T > 0 */
     const float *terminal_V;   /* optional [n_v][n_soc][n_t] added to the terminal cost; NULL = none
-                                  (host memory, or device memory with DP_TERMINAL_DEVICE)          */
+                                  (host memory, or device memory with DP_TERMINAL_DEVICE).  Values
+                                  must not be negative (costs are not; the sweep relies on it): a
+                                  negative host value fails the build with DP_EINVAL, a negative
+                                  device value sets the device error word (dp_device_check); NaN
+                                  makes the node J_inf                                             */
     uint32_t flags;            /* DP_WAIT_AT_RED, DP_TERMINAL_DEVICE */
     const double *light_yellow;/* [n_lights] yellow duration Y >= 0 before red, Y + R <= C: yellow iff
                                   (t_abs - O) mod C in [C - Y, C) (three-phase signals, Sec. III), or
@@ -198,9 +202,10 @@ int dp_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0_dev, int16_
 int dp_solve_static(dp_plan *p, void *J, void *pi, float *V0_dev, int16_t *u0_dev, void *stream);
 
 /* One backward step k of instance `inst` from a caller-provided J_{k+1} slab
- * (device float [n_v][n_soc][n_t]) into J_out / pi_out (device slabs, not
- * aliasing J_next), with the configuration dp_solve uses for that stage; the
- * stage tables are rebuilt in `scratch`. */
+ * (device float [n_v][n_soc][n_t], values >= 0 as every value slab of a
+ * solve; a negative value gives unspecified minima) into J_out / pi_out
+ * (device slabs, not aliasing J_next), with the configuration dp_solve uses
+ * for that stage; the stage tables are rebuilt in `scratch`. */
 int dp_stage(dp_plan *p, int32_t inst, int32_t k, const float *J_next, float *J_out,
              int16_t *pi_out, void *scratch, void *stream);
 
@@ -358,7 +363,8 @@ int dp_executed_evaluations(dp_plan *p, int64_t *counts, void *stream);
 
 /* Synchronises on `stream` and reads the plan's device error word, which
  * kernels set when they meet a condition the host checks could not exclude
- * (a SoC cell offset outside the int8 field of the sweep's records).
+ * (a SoC cell offset outside the int8 field of the sweep's records, a
+ * persistent sweep that gave up waiting, a negative device terminal_V).
  * DP_OK if it is clear; else DP_EDEVICE with the condition named in
  * dp_last_error(), and the word is cleared.  Results of the solves enqueued
  * before such an error are not to be used. */

@@ -245,6 +245,13 @@ int validate(const dp_problem_desc &d, int b)
             (void)hipGetLastError();
             return fail(DP_EINVAL, "instance %d: DP_TERMINAL_DEVICE but terminal_V is not device memory", b);
         }
+    } else if (d.terminal_V) {
+        // costs are non-negative (the sweep's minimum relies on it); a NaN
+        // terminal value makes the node J_inf
+        const long S = (long)d.n_v * d.n_soc * d.n_t;
+        for (long n = 0; n < S; n++)
+            if (d.terminal_V[n] < 0.0f)
+                return fail(DP_EINVAL, "instance %d: terminal_V[%ld] = %g is negative", b, n, (double)d.terminal_V[n]);
     }
     return DP_OK;
 }
@@ -1308,7 +1315,7 @@ static int enqueue_solve(dp_plan *p, void *J, void *pi, void *scratch, float *V0
 {
     if (p->persist) return enqueue_persist(p, J, pi, scratch, V0_dev, u0_dev, s, timing);
     const int n_inst = (int)p->inst.size();
-    if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, s))
+    if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, p->dev_err, s))
         return hip_fail(hipGetLastError(), "terminal launch");
     if (launch_fill_i32(queue_slot(p, scratch, 0), 8L * p->n_q_slots, 0, s) ||
         launch_fill_i32((int *)p->dev_count, 2L * (long)p->inst.size(), 0, s))
@@ -1401,7 +1408,7 @@ static int enqueue_persist(dp_plan *p, void *J, void *pi, void *scratch, float *
     int *pc = (int *)((char *)scratch + p->scr_pc);
     if (launch_fill_i32(pc, p->n_pc, 0, s) || launch_fill_i32((int *)p->dev_count, 2L * n_inst, 0, s))
         return hip_fail(hipGetLastError(), "counter reset launch");
-    if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, s))
+    if (launch_terminal_jobs(p->dev_insts, n_inst, p->max_slab, J, p->dev_roll + 3 * n_inst, p->dev_err, s))
         return hip_fail(hipGetLastError(), "terminal launch");
     const StageBase base = stage_base(p, J, pi, scratch);
     {
@@ -1784,9 +1791,10 @@ int dp_device_check(dp_plan *p, void *stream)
     e = hipMemcpyAsync(p->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "device error word reset");
-    return fail(DP_EDEVICE, "device error word 0x%x:%s%s", w,
+    return fail(DP_EDEVICE, "device error word 0x%x:%s%s%s", w,
                 (w & kDevErrCellOffset) ? " a SoC cell offset did not fit its int8 record field;" : "",
-                (w & kDevErrWait) ? " a persistent sweep gave up waiting for a stage;" : "");
+                (w & kDevErrWait) ? " a persistent sweep gave up waiting for a stage;" : "",
+                (w & kDevErrNegative) ? " a terminal value (device terminal_V) was negative;" : "");
 }
 
 int dp_sweep_time(dp_plan *p, double *ms, int32_t *launches)

@@ -11,7 +11,7 @@ namespace ecodp {
 // Every instance's terminal slab (grid y = instance) and root step in one
 // launch each; per-instance byte offsets of J_N and J_1 from J.
 int launch_terminal_jobs(const DevInst *insts, int n_inst, long max_slab, void *J, const long long *jN_off,
-                         hipStream_t s);
+                         int *err, hipStream_t s);
 int launch_terminal_shift(const float *src, long nvs, int n_src, double h_src, double t_shift, int n_dst, double h_dst,
                           double Jinf, float *dst, hipStream_t s);
 int launch_stage_table(const DevInst &P, int k, StageEntry *st, BatEntry *bat, unsigned long long *count,

@@ -9,9 +9,11 @@ namespace ecodp {
 // ---------------------------------------------------------------- terminal --
 
 // J_N = min(J_inf, w_soc (xi_j - xi_ref)^2 + terminal_V) in FP64, one FP32
-// rounding; nodes above the stage-N speed limit take J_inf.
+// rounding; nodes above the stage-N speed limit take J_inf.  A negative
+// terminal_V value (the sweep's minimum assumes non-negative costs) sets
+// kDevErrNegative in the device error word.
 __global__ void k_terminal_jobs(const DevInst *__restrict__ insts, char *__restrict__ J,
-                                const long long *__restrict__ jN_off)
+                                const long long *__restrict__ jN_off, int *__restrict__ err)
 {
 #pragma clang fp contract(off)
     const DevInst &P = insts[blockIdx.y];
@@ -26,7 +28,11 @@ __global__ void k_terminal_jobs(const DevInst *__restrict__ insts, char *__restr
         const double v = P.v_lo + i * P.hv;
         const double xi = P.s_lo + j * P.hs;
         double val = P.wsoc * (xi - P.xiref) * (xi - P.xiref);
-        if (P.terminal_V) val += (double)P.terminal_V[n];
+        if (P.terminal_V) {
+            const float tv = P.terminal_V[n];
+            if (tv < 0.0f) atomicOr(err, kDevErrNegative);
+            val += (double)tv;
+        }
         if (v > P.vmax[P.N] || !(val < P.Jinf)) val = P.Jinf;
         JN[n] = (float)val;
     }
@@ -332,12 +338,12 @@ __global__ void __launch_bounds__(256) k_root_jobs(const DevInst *__restrict__ i
 // ------------------------------------------------------------------ launch --
 
 int launch_terminal_jobs(const DevInst *insts, int n_inst, long max_slab, void *J, const long long *jN_off,
-                         hipStream_t s)
+                         int *err, hipStream_t s)
 {
     long blocks = (max_slab + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_terminal_jobs, dim3((unsigned)blocks, n_inst), dim3(256), 0, s, insts, (char *)J, jN_off);
+    hipLaunchKernelGGL(k_terminal_jobs, dim3((unsigned)blocks, n_inst), dim3(256), 0, s, insts, (char *)J, jN_off, err);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

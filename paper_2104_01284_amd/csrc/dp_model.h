@@ -138,6 +138,7 @@ struct StageBase {
 // Bits of the plan's device error word (sticky until read by the host).
 constexpr int kDevErrCellOffset = 1;   // a SoC cell offset did not fit the records' int8 field
 constexpr int kDevErrWait = 2;         // a persistent sweep gave up waiting for a stage
+constexpr int kDevErrNegative = 4;     // a device terminal_V value was negative (costs must not be)
 
 // One (instance, stage) job of the persistent sweep: the stage job, the items
 // of the instance's later stages that must be counted before it starts, and

@@ -443,13 +443,18 @@ __device__ __forceinline__ void sweep_item(const StageBase &B, const StageJob &j
     const int m = (wave - grp * (gthreads >> 6)) * 63 + lane;
     const bool out_lane = lane < 63 && m < nt;
     const float Jinf = P.Jinf;
-    float best[R];
-    int bu[R];
+    // The running minimum of a row as one FP64 word: the high half holds the
+    // FP32 value's bits with the sign cleared, the low half the control's
+    // position in the node's visit order (plus one) above its index u.  Every
+    // value is non-negative (stage and terminal costs are; a NaN candidate's
+    // cleared bits sit above +inf), and the FP64 order of such words is the
+    // order of the values, then of the positions: one v_min_f64 per row keeps
+    // the first minimum in visit order (the order a strict < keeps) without a
+    // compare and two selects, and J_inf at position 0 (no control) loses to
+    // any value below J_inf and beats J_inf itself.
+    double bk[R];
 #pragma unroll
-    for (int q = 0; q < R; q++) {
-        best[q] = Jinf;
-        bu[q] = -1;
-    }
+    for (int q = 0; q < R; q++) bk[q] = __hiloint2double(__float_as_int(Jinf), 0);
     double v;
     {
 #pragma clang fp contract(off)
@@ -640,19 +645,30 @@ __device__ __forceinline__ void sweep_item(const StageBase &B, const StageJob &j
                     }
                 }
             }
-            // the next control's record, in flight during the minimum update
+            // the next control's record
             W = nx[wofs + wlane];
             S = nx[rec_scalars(JT) + slane];
+            {
+                const int rk = ((c0 + cr + 1) << 16) | u;   // positions and u below 2^15
 #pragma unroll
-            for (int q = 0; q < R; q++) {
-                const bool upd = Qv[q] < best[q];
-                best[q] = upd ? Qv[q] : best[q];
-                bu[q] = upd ? u : bu[q];
+                for (int q = 0; q < R; q++) {
+                    const double cand = __hiloint2double(__float_as_int(Qv[q]) & 0x7fffffff, rk);
+                    asm("v_min_f64 %0, %1, %2" : "=v"(bk[q]) : "v"(cand), "v"(bk[q]));
+                }
             }
         }
     }
     if (threadIdx.x == 0 && nrec > 0)
         atomicAdd(B.count + jb.inst, (unsigned long long)nrec * (unsigned long long)(jc * nt));
+    // the minimum's value and control (position 0: none)
+    float best[R];
+    int bu[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        best[q] = __int_as_float(__double2hiint(bk[q]));
+        const int rk = __double2loint(bk[q]);
+        bu[q] = rk > 0 ? (rk & 0xffff) : -1;
+    }
     if (out_lane && nsplit > 1) {
         // partial minimum of this control slice; the combine kernel finishes
         const long plane_nodes = (long)P.n_v * SV;

@@ -206,3 +206,20 @@ def test_device_terminal_flag_needs_device_memory(lib):
     assert rc in (L.DP_EINVAL, L.DP_EDEVICE)
     d.d.terminal_V = None
     assert lib.dp_build_problem(C.byref(d.d), 1, None, 0, C.byref(h)) == L.DP_EINVAL
+
+
+def test_negative_host_terminal_values_rejected(lib):
+    """Costs are non-negative (the sweep's running minimum relies on it): a
+    host terminal_V with a negative value fails the build before any device
+    use; zeros and NaN (a J_inf node) pass the check."""
+    inst = ins.plain()
+    tv = np.zeros((21, 11, 31), dtype=np.float32)
+    tv[3, 4, 5] = np.nan
+    tv[7, 2, 30] = -1.0e-3
+    inst["terminal_V"] = tv
+    d = _Desc(inst)
+    h = C.c_void_p()
+    assert lib.dp_build_problem(C.byref(d.d), 1, None, 0, C.byref(h)) == L.DP_EINVAL
+    msg = C.create_string_buffer(256)
+    lib.dp_last_error(msg, 256)
+    assert b"negative" in msg.value and b"terminal_V" in msg.value

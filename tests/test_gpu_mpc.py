@@ -197,3 +197,22 @@ def test_closed_loop_drives_to_route_end(torch):
         assert res["fuel_g"] == pytest.approx(ref["fuel"], rel=1e-9)
         row = L.DpLoopRow()
         assert loop.lib.dp_loop_step(loop._h, C.byref(row)) == L.DP_ESTATE
+
+
+def test_negative_device_terminal_value_reported(torch):
+    """A device terminal_V cannot be checked on the host: a negative value
+    sets the plan's device error word, which dp_device_check reports (costs
+    must be non-negative); the word is cleared by the report."""
+    inst = ins.plain()
+    tv = np.zeros((21, 11, 31), dtype=np.float32)
+    tv[5, 5, 10] = -2.0
+    from paper_2104_01284_amd._lib import DPError
+    plan = Plan([dict(inst, terminal_V=torch.from_numpy(tv).cuda())], store_all=True)
+    plan.solve()
+    with pytest.raises(DPError) as e:
+        plan.device_check()
+    assert "negative" in str(e.value)
+    plan.device_check()
+    ok = Plan([dict(inst, terminal_V=torch.from_numpy(np.abs(tv)).cuda())], store_all=True)
+    ok.solve()
+    ok.device_check()
