@@ -880,30 +880,16 @@ __global__ void k_sweep_combine(StageBase B)
     const int16_t *__restrict__ part_u = (const int16_t *)(B.scr + jb.pu);
     const float Jinf = (float)P.Jinf;
     const long S = (long)P.n_v * P.n_s * P.n_t;
-    constexpr int kInFlight = 16;   // slices whose partial values are loaded at once
     for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < S; n += (long)gridDim.x * blockDim.x) {
-        // first minimum in slice order: all loads of the first kInFlight
-        // slices issued before any comparison, then the rest one by one; the
-        // control is read from the winning slice only
-        float xs[kInFlight];
-#pragma unroll
-        for (int sp = 0; sp < kInFlight; sp++) xs[sp] = sp < nsplit ? part_v[sp * S + n] : Jinf;
-        float J = xs[0];
-        int win = 0;
-#pragma unroll
-        for (int sp = 1; sp < kInFlight; sp++)
-            if (sp < nsplit && xs[sp] < J) {
-                J = xs[sp];
-                win = sp;
-            }
-        for (int sp = kInFlight; sp < nsplit; sp++) {
+        float J = part_v[n];
+        int pu = part_u[n];
+        for (int sp = 1; sp < nsplit; sp++) {
             const float x = part_v[sp * S + n];
             if (x < J) {
                 J = x;
-                win = sp;
+                pu = part_u[sp * S + n];
             }
         }
-        int pu = part_u[win * S + n];
         if (tl != nullptr) {
             const int m = (int)(n % P.n_t);
             const TLEntry t = tl[m];
