@@ -270,8 +270,11 @@ int dp_terminal_from_values(const float *src, int32_t n_v, int32_t n_soc, int32_
  *      admissible control (u_0* = -1) or a non-finite step stops the loop
  *      with status DP_EINFEASIBLE.
  * The row describes the step; its status is the loop's.  After the last
- * stage, or once stopped, dp_loop_step returns DP_ESTATE.  A loop must not be
- * used from two host threads at once. */
+ * stage, or once stopped, dp_loop_step returns DP_ESTATE.  Each step reads
+ * the horizon plan's device error word (dp_device_check) after its solve and
+ * returns DP_EDEVICE without moving the vehicle when a kernel set it;
+ * dp_loop_create checks the full-route solve the same way.  A loop must not
+ * be used from two host threads at once. */
 typedef struct dp_loop dp_loop;
 
 typedef struct {

@@ -176,6 +176,7 @@ int dp_loop_create(const dp_problem_desc *route, int32_t horizon, double t_f, in
     if (!rc) rc = dp_solve(L->full, L->fJ, L->fpi, L->fscr, L->fV0, L->fu0, L->stream);
     if (!rc && (e = hipStreamSynchronize(L->stream)) != hipSuccess)
         rc = api_fail(DP_EDEVICE, "loop: full-route solve: %s", hipGetErrorString(e));
+    if (!rc) rc = dp_device_check(L->full, L->stream);   // a condition the kernels met (DP_EDEVICE)
     if (rc) {
         loop_free(L);
         return rc;
@@ -308,6 +309,7 @@ int dp_loop_step(dp_loop *L, dp_loop_row *row)
         e = hipMemcpyAsync(L->host + 16, w.V0, sizeof(float), hipMemcpyDeviceToHost, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return api_fail(DP_EDEVICE, "loop: step %d: %s", s, hipGetErrorString(e));
+    if ((rc = dp_device_check(w.p, L->stream))) return rc;   // the step's solve is then not used
     if (L->timing) {
         double ms = 0.0;
         int32_t n = 0;
